@@ -1,0 +1,169 @@
+"""CPU oracle for the progressive spatio-temporal filtering hash path.
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke entry point and the benchmark's
+CPU-baseline leg may use it; the library never does.  The arithmetic lives in
+``psf_oracle.cpp`` (binary64, ``std::map``); this module only marshals numpy
+arrays through ctypes.  It imports nothing from the HIP package.
+
+Sections followed: Sec. 2.1 Eq. 5-6 (counts and weighted means per basis
+function), Sec. 2.4 Eq. 10-11 (temporal blend, counter reset), Sec. 2.6
+(spatio-directional hashing; the key specification is this project's, written
+out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpsf_oracle.so")
+_lib = None
+
+ALPHA_PAPER, ALPHA_CONST, ALPHA_LINEAR = 0, 1, 2
+RESET_COUNTERS, RESET_CLEAR = 1, 2
+FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
+
+
+class _Records(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p * 13)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (no GPU code involved)."""
+    from . import build as _b
+    return _b.build(force=force)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    lib.orc_create.restype = vp
+    lib.orc_create.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_float, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                               ctypes.c_int, ctypes.c_float, ctypes.c_float]
+    lib.orc_destroy.argtypes = [vp]
+    lib.orc_keys.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
+    lib.orc_set_filter.argtypes = [vp, vp, u64]
+    lib.orc_insert.argtypes = [vp, ctypes.POINTER(_Records), u64]
+    lib.orc_update.restype = u64
+    lib.orc_update.argtypes = [vp]
+    lib.orc_query.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
+    lib.orc_reset.argtypes = [vp, u32]
+    lib.orc_count.restype = u64
+    lib.orc_count.argtypes = [vp]
+    lib.orc_export.restype = u64
+    lib.orc_export.argtypes = [vp, vp, vp, vp, vp, vp, u64]
+    lib.orc_counters.argtypes = [vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class _Pack:
+    """Holds contiguous float32 copies alive while the C call runs."""
+
+    def __init__(self, rec: dict, n: int):
+        self.keep = []
+        self.s = _Records()
+        for i, name in enumerate(FIELDS):
+            a = rec.get(name)
+            if a is None:
+                self.s.f[i] = None
+                continue
+            a = _f32(a)
+            if a.shape[0] < n:
+                raise ValueError(f"field {name} shorter than n")
+            self.keep.append(a)
+            self.s.f[i] = a.ctypes.data
+
+
+class Oracle:
+    """One hash table, mirrored in binary64 on the host."""
+
+    def __init__(self, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0, max_level=15,
+                 normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
+                 alpha_mode=ALPHA_PAPER, alpha=0.2, t_max=5.0, **_ignored):
+        self._lib = _load()
+        cam_arr = (ctypes.c_float * 3)(*[float(c) for c in cam])
+        self._h = self._lib.orc_create(cam_arr, float(np.float32(kappa)), int(e_min),
+                                       int(max_level), int(normal_bins_log2),
+                                       int(dir_bins_log2), float(np.float32(rough_thr)),
+                                       int(alpha_mode), float(np.float32(alpha)),
+                                       float(np.float32(t_max)))
+
+    def close(self):
+        if self._h:
+            self._lib.orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _n(rec):
+        return int(np.asarray(rec["px"]).shape[0])
+
+    def keys(self, rec):
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        out = np.empty(n, dtype=np.uint64)
+        ovf = np.empty(n, dtype=np.uint8)
+        self._lib.orc_keys(self._h, ctypes.byref(p.s), n, out.ctypes.data, ovf.ctypes.data)
+        return out, ovf
+
+    def set_filter(self, keys):
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        self._lib.orc_set_filter(self._h, k.ctypes.data if k.size else None, int(k.size))
+
+    def insert(self, rec):
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        self._lib.orc_insert(self._h, ctypes.byref(p.s), n)
+
+    def update(self) -> int:
+        return int(self._lib.orc_update(self._h))
+
+    def query(self, rec):
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        out = np.zeros((3, n), dtype=np.float64)
+        found = np.zeros(n, dtype=np.uint8)
+        self._lib.orc_query(self._h, ctypes.byref(p.s), n, out.ctypes.data, found.ctypes.data)
+        return out, found
+
+    def reset(self, what: int):
+        self._lib.orc_reset(self._h, int(what))
+
+    def count(self) -> int:
+        return int(self._lib.orc_count(self._h))
+
+    def export(self):
+        cap = self.count()
+        keys = np.zeros(cap, dtype=np.uint64)
+        n_new = np.zeros(cap, dtype=np.uint64)
+        c_old = np.zeros(cap, dtype=np.uint64)
+        L = np.zeros((3, cap), dtype=np.float64)
+        s = np.zeros((3, cap), dtype=np.float64)
+        if cap:
+            got = self._lib.orc_export(self._h, keys.ctypes.data, n_new.ctypes.data,
+                                       c_old.ctypes.data, L.ctypes.data, s.ctypes.data, cap)
+            assert got == cap
+        return {"keys": keys, "n_new": n_new, "c_old": c_old, "L": L, "s": s}
+
+    def counters(self):
+        a = np.zeros(3, dtype=np.uint64)
+        self._lib.orc_counters(self._h, a[0:].ctypes.data, a[1:].ctypes.data, a[2:].ctypes.data)
+        return {"skipped": int(a[0]), "coord_overflow": int(a[1]), "inserted": int(a[2])}

@@ -1,0 +1,372 @@
+// Reference oracle for progressive spatio-temporal filtering (PSTF).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, single-threaded CPU
+// statement of what the hash-filter hot path computes.  It exists so that the
+// HIP library can be checked against it; nothing in the product links it.
+// Only tests, the smoke entry point and the CPU-baseline leg of the benchmark
+// may load it.  It shares no code with the HIP library.
+//
+// What it follows (Pantaleoni, "Online path sampling control with progressive
+// spatio-temporal filtering", arXiv 2005.07547):
+//   * Sec. 2.1, Eq. 5-6: per basis function h, a counter c_h (sum of box-basis
+//     memberships times MIS weights) and the weighted sample mean of the path
+//     tail estimates.  Box basis, weight w = 1 (Algorithm 1 sets the MIS
+//     weight to 1 when no other technique is used).
+//   * Sec. 2.4, Eq. 10-11: temporal blend of the new mean into the previous
+//     approximant with alpha = max(sqrt(c_new / (c_old + c_new)), 1/T_max);
+//     c_old is the cumulative count up to the previous frame.  The same
+//     section names the two limiting cases used as alternative modes: linear
+//     accumulation (no square root) and exponential weighting (constant alpha).
+//     Counters may be zeroed globally (reset).
+//   * Sec. 2.6: the basis is a grid over position times a grid over direction,
+//     i.e. a spatio-directional hash.  The paper leaves the exact quantisation
+//     to Binder et al. and the level choice to a footprint heuristic; the key
+//     function below is this project's fixed specification of both (positions
+//     on power-of-two grids whose level grows with camera distance, octahedral
+//     bins for the normal and, for glossy vertices, for the outgoing
+//     direction).  Floating point that decides an integer is done in IEEE
+//     binary32 exactly as specified (no contraction), so that any correct
+//     implementation obtains the same bits.
+//   * Algorithm 1: a lookup of the approximant at a vertex reads the state
+//     left by the last completed temporal blend.
+//
+// Accumulation and blending are in binary64.  The table is a std::map with no
+// capacity limit.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (see build.py).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <set>
+#include <vector>
+
+namespace {
+
+struct Config {
+  float cam[3];
+  float kappa;        // level scale; 0 selects a fixed level 0
+  int e_min;          // finest cell edge is 2^e_min
+  int max_level;      // 0..15
+  int normal_bins_log2;  // 0..2  (B = 1..4 bins per octahedral axis)
+  int dir_bins_log2;     // 0..3  (B = 1..8)
+  float rough_thr;    // glossy iff roughness < rough_thr (strict)
+  int alpha_mode;     // 0 = Eq. 11, 1 = constant alpha, 2 = linear (no sqrt)
+  float alpha;        // constant-mode alpha
+  float t_max;        // Eq. 11 temporal window bound (> 0)
+};
+
+struct Cell {
+  uint64_t n_new = 0;            // c_h^new of the current frame
+  double s[3] = {0.0, 0.0, 0.0}; // sum of the frame's sample values
+  uint64_t c_old = 0;            // cumulative count up to the previous frame
+  double L[3] = {0.0, 0.0, 0.0}; // approximant
+};
+
+struct Oracle {
+  Config cfg;
+  std::map<uint64_t, Cell> cells;
+  bool filtered = false;
+  std::set<uint64_t> filter;
+  uint64_t skipped = 0;
+  uint64_t coord_overflow = 0;
+  uint64_t inserted = 0;
+};
+
+// --------------------------------------------------------------------------
+// Key function K (project specification; Sec. 2.6 leaves it open).
+
+bool finite3(float a, float b, float c) {
+  return std::isfinite(a) && std::isfinite(b) && std::isfinite(c);
+}
+
+// Level from camera distance: floor(0.5 * log2(kappa * d^2)) clamped to
+// [0, max_level], read from the binary32 exponent of kappa * d^2.
+int level_of(const Config& c, float px, float py, float pz) {
+  if (c.kappa == 0.0f) return 0;
+  float dx = px - c.cam[0];
+  float dy = py - c.cam[1];
+  float dz = pz - c.cam[2];
+  float xx = dx * dx;
+  float yy = dy * dy;
+  float zz = dz * dz;
+  float d2 = xx + yy;
+  d2 = d2 + zz;
+  float q = d2 * c.kappa;
+  uint32_t bits;
+  std::memcpy(&bits, &q, sizeof bits);
+  int field = (int)((bits >> 23) & 0xffu);
+  int e = (field == 0) ? -127 : field - 127;
+  // floor(e / 2) for negative e as well
+  int lvl = (e >= 0) ? e / 2 : -((-e + 1) / 2);
+  if (lvl < 0) lvl = 0;
+  if (lvl > c.max_level) lvl = c.max_level;
+  return lvl;
+}
+
+// Grid coordinate floor(p * 2^-(e_min + lvl)); reports whether it lies
+// outside the signed 16-bit range that the key stores.  The returned value is
+// taken modulo 2^16 by the caller.
+int64_t grid_coord(float p, int shift, bool* overflow) {
+  float scaled = std::ldexp(p, -shift);
+  float f = std::floor(scaled);
+  if (!(f >= -32768.0f && f < 32768.0f)) *overflow = true;
+  // clamp into a range that converts exactly, then convert
+  if (f < -2147483648.0f) f = -2147483648.0f;
+  if (f > 2147483520.0f) f = 2147483520.0f;
+  return (int64_t)f;
+}
+
+// Octahedral bin index iu * B + iw of direction v with B = 2^b bins per axis.
+uint32_t octa_bin(float vx, float vy, float vz, int b) {
+  const int B = 1 << b;
+  float ax = std::fabs(vx), ay = std::fabs(vy), az = std::fabs(vz);
+  float a = ax + ay;
+  a = a + az;
+  float u = 0.0f, w = 0.0f;
+  if (a > 0.0f) {
+    u = vx / a;
+    w = vy / a;
+  }
+  if (vz < 0.0f) {
+    float su = (u >= 0.0f) ? 1.0f : -1.0f;
+    float sw = (w >= 0.0f) ? 1.0f : -1.0f;
+    float nu = (1.0f - std::fabs(w)) * su;
+    float nw = (1.0f - std::fabs(u)) * sw;
+    u = nu;
+    w = nw;
+  }
+  float fu = u * 0.5f;
+  fu = fu + 0.5f;
+  fu = fu * (float)B;
+  float fw = w * 0.5f;
+  fw = fw + 0.5f;
+  fw = fw * (float)B;
+  int iu = (int)std::floor(fu);
+  int iw = (int)std::floor(fw);
+  if (iu > B - 1) iu = B - 1;
+  if (iw > B - 1) iw = B - 1;
+  if (iu < 0) iu = 0;
+  if (iw < 0) iw = 0;
+  return (uint32_t)(iu * B + iw);
+}
+
+struct KeyResult {
+  bool valid;
+  bool overflow;
+  uint64_t key;
+};
+
+// rough may be null (all vertices diffuse).
+KeyResult key_of(const Config& c, float px, float py, float pz, float nx, float ny, float nz,
+                 float ox, float oy, float oz, const float* rough) {
+  KeyResult r{false, false, 0};
+  if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return r;
+  bool glossy = false;
+  if (rough) {
+    if (!std::isfinite(*rough)) return r;
+    glossy = (*rough < c.rough_thr);
+    if (glossy && !finite3(ox, oy, oz)) return r;
+  }
+  int lvl = level_of(c, px, py, pz);
+  int shift = c.e_min + lvl;
+  bool ovf = false;
+  int64_t ix = grid_coord(px, shift, &ovf);
+  int64_t iy = grid_coord(py, shift, &ovf);
+  int64_t iz = grid_coord(pz, shift, &ovf);
+  uint64_t nb = octa_bin(nx, ny, nz, c.normal_bins_log2);
+  uint64_t db = glossy ? octa_bin(ox, oy, oz, c.dir_bins_log2) : 0;
+  uint64_t k = 0;
+  k |= (uint64_t)lvl << 59;
+  k |= (uint64_t)(glossy ? 1 : 0) << 58;
+  k |= db << 52;
+  k |= nb << 48;
+  k |= ((uint64_t)ix & 0xffffu);
+  k |= ((uint64_t)iy & 0xffffu) << 16;
+  k |= ((uint64_t)iz & 0xffffu) << 32;
+  r.valid = true;
+  r.overflow = ovf;
+  r.key = k;
+  return r;
+}
+
+double alpha_of(const Config& c, uint64_t n_new, uint64_t c_old) {
+  double n = (double)n_new, o = (double)c_old;
+  switch (c.alpha_mode) {
+    case 1:  // constant alpha (exponential weighting); first touch takes the mean
+      return c_old == 0 ? 1.0 : (double)c.alpha;
+    case 2:  // linear accumulation
+      return n / (o + n);
+    default: {  // Eq. 11
+      double a = std::sqrt(n / (o + n));
+      double floor_a = 1.0 / (double)c.t_max;
+      return a > floor_a ? a : floor_a;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Record arrays: 13 pointers px,py,pz,nx,ny,nz,ox,oy,oz,r,g,b,rough.  Any of
+// ox..oz, r..b and rough may be null where not used (rough null = diffuse).
+struct orc_records {
+  const float* f[13];
+};
+
+void* orc_create(const float* cam, float kappa, int e_min, int max_level, int normal_bins_log2,
+                 int dir_bins_log2, float rough_thr, int alpha_mode, float alpha, float t_max) {
+  Oracle* o = new Oracle();
+  o->cfg.cam[0] = cam[0];
+  o->cfg.cam[1] = cam[1];
+  o->cfg.cam[2] = cam[2];
+  o->cfg.kappa = kappa;
+  o->cfg.e_min = e_min;
+  o->cfg.max_level = max_level;
+  o->cfg.normal_bins_log2 = normal_bins_log2;
+  o->cfg.dir_bins_log2 = dir_bins_log2;
+  o->cfg.rough_thr = rough_thr;
+  o->cfg.alpha_mode = alpha_mode;
+  o->cfg.alpha = alpha;
+  o->cfg.t_max = t_max;
+  return o;
+}
+
+void orc_destroy(void* h) { delete static_cast<Oracle*>(h); }
+
+static KeyResult key_at(const Config& c, const orc_records* r, uint64_t i) {
+  const float* const* f = r->f;
+  float ox = f[6] ? f[6][i] : 0.0f, oy = f[7] ? f[7][i] : 0.0f, oz = f[8] ? f[8][i] : 0.0f;
+  return key_of(c, f[0][i], f[1][i], f[2][i], f[3][i], f[4][i], f[5][i], ox, oy, oz,
+                f[12] ? &f[12][i] : nullptr);
+}
+
+// Keys of n records; invalid (skipped) records get all-ones.  overflow[i]
+// (optional) receives 1 where a grid coordinate left the 16-bit range.
+void orc_keys(void* h, const orc_records* r, uint64_t n, uint64_t* out, uint8_t* overflow) {
+  Oracle* o = static_cast<Oracle*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    KeyResult k = key_at(o->cfg, r, i);
+    out[i] = k.valid ? k.key : ~0ull;
+    if (overflow) overflow[i] = k.overflow ? 1 : 0;
+  }
+}
+
+// Restrict accumulation to a set of keys (sampled parity at large sizes).
+// n = 0 removes the restriction.
+void orc_set_filter(void* h, const uint64_t* keys, uint64_t n) {
+  Oracle* o = static_cast<Oracle*>(h);
+  o->filter.clear();
+  o->filtered = n > 0;
+  for (uint64_t i = 0; i < n; ++i) o->filter.insert(keys[i]);
+}
+
+// Eq. 5-6 with box basis and w = 1: count and sum per cell, in array order.
+void orc_insert(void* h, const orc_records* r, uint64_t n) {
+  Oracle* o = static_cast<Oracle*>(h);
+  const float* const* f = r->f;
+  for (uint64_t i = 0; i < n; ++i) {
+    float R = f[9][i], G = f[10][i], B = f[11][i];
+    KeyResult k = key_at(o->cfg, r, i);
+    if (!k.valid || !finite3(R, G, B)) {
+      o->skipped++;
+      continue;
+    }
+    if (k.overflow) o->coord_overflow++;
+    if (o->filtered && o->filter.count(k.key) == 0) continue;
+    Cell& c = o->cells[k.key];
+    c.n_new += 1;
+    c.s[0] += (double)R;
+    c.s[1] += (double)G;
+    c.s[2] += (double)B;
+    o->inserted++;
+  }
+}
+
+// Eq. 10-11 for every cell touched since the last update.  Untouched cells
+// keep their state.  Returns the number of cells blended.
+uint64_t orc_update(void* h) {
+  Oracle* o = static_cast<Oracle*>(h);
+  uint64_t touched = 0;
+  for (auto& kv : o->cells) {
+    Cell& c = kv.second;
+    if (c.n_new == 0) continue;
+    double a = alpha_of(o->cfg, c.n_new, c.c_old);
+    for (int ch = 0; ch < 3; ++ch) {
+      double mean = c.s[ch] / (double)c.n_new;
+      c.L[ch] = (1.0 - a) * c.L[ch] + a * mean;
+      c.s[ch] = 0.0;
+    }
+    c.c_old += c.n_new;
+    c.n_new = 0;
+    touched++;
+  }
+  return touched;
+}
+
+// Lookup: the approximant of the query's cell if that cell has been blended
+// at least once since its counters were last cleared; otherwise zero.
+void orc_query(void* h, const orc_records* r, uint64_t n, double* out_rgb, uint8_t* found) {
+  Oracle* o = static_cast<Oracle*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    KeyResult k = key_at(o->cfg, r, i);
+    double v[3] = {0.0, 0.0, 0.0};
+    uint8_t hit = 0;
+    if (k.valid) {
+      auto it = o->cells.find(k.key);
+      if (it != o->cells.end() && it->second.c_old > 0) {
+        hit = 1;
+        for (int ch = 0; ch < 3; ++ch) v[ch] = it->second.L[ch];
+      }
+    }
+    out_rgb[i] = v[0];
+    out_rgb[n + i] = v[1];
+    out_rgb[2 * n + i] = v[2];
+    if (found) found[i] = hit;
+  }
+}
+
+// what bit 0: zero c_old of every cell (global counter reset, Sec. 2.4);
+// bit 1: remove every cell.
+void orc_reset(void* h, uint32_t what) {
+  Oracle* o = static_cast<Oracle*>(h);
+  if (what & 2u) {
+    o->cells.clear();
+    return;
+  }
+  if (what & 1u)
+    for (auto& kv : o->cells) kv.second.c_old = 0;
+}
+
+uint64_t orc_count(void* h) { return static_cast<Oracle*>(h)->cells.size(); }
+
+// Cells in ascending key order.  L and s are 3 x cap (SoA).  Returns the
+// number written.
+uint64_t orc_export(void* h, uint64_t* keys, uint64_t* n_new, uint64_t* c_old, double* L,
+                    double* s, uint64_t cap) {
+  Oracle* o = static_cast<Oracle*>(h);
+  uint64_t i = 0;
+  for (auto& kv : o->cells) {
+    if (i >= cap) break;
+    keys[i] = kv.first;
+    if (n_new) n_new[i] = kv.second.n_new;
+    if (c_old) c_old[i] = kv.second.c_old;
+    for (int ch = 0; ch < 3; ++ch) {
+      if (L) L[ch * cap + i] = kv.second.L[ch];
+      if (s) s[ch * cap + i] = kv.second.s[ch];
+    }
+    ++i;
+  }
+  return i;
+}
+
+void orc_counters(void* h, uint64_t* skipped, uint64_t* coord_overflow, uint64_t* inserted) {
+  Oracle* o = static_cast<Oracle*>(h);
+  *skipped = o->skipped;
+  *coord_overflow = o->coord_overflow;
+  *inserted = o->inserted;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""Synthetic workloads shaped like the paper's measurements.
+
+The paper's scenes (door ajar, staircase, arch interior) and renderer are not
+available; these procedural stand-ins reproduce the shapes that matter for the
+hash path: image size, samples per pixel, vertices per path, wavefront record
+order, diffuse/glossy mix and radiance distribution.
+
+Each workload is a plain dict.  ``table`` holds the filter configuration
+(identical for the oracle and the library); ``gen`` holds the generator
+parameters.  ``kappa`` is the camera-distance level scale
+(k_s * theta_pix / 2^e_min)^2 computed once here in float32 and handed to both
+sides as the same float.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import Scene
+
+ALPHA_PAPER, ALPHA_CONST, ALPHA_LINEAR = 0, 1, 2
+
+
+def kappa_for(fov_y_deg: float, height: int, k_s: float, e_min: int) -> float:
+    f32 = np.float32
+    theta = f32(2.0) * f32(math.tan(math.radians(fov_y_deg) / 2.0)) / f32(height)
+    v = f32(k_s) * theta / f32(2.0 ** e_min)
+    return float(f32(v * v))
+
+
+def _table(log2_slots, cam, fov, height, k_s, e_min, alpha_mode=ALPHA_PAPER, alpha=0.2,
+           t_max=5.0, rough_thr=0.3, max_level=15, max_probe=64):
+    return {
+        "log2_slots": log2_slots, "max_probe": max_probe, "cam": tuple(float(c) for c in cam),
+        "kappa": kappa_for(fov, height, k_s, e_min), "e_min": e_min, "max_level": max_level,
+        "normal_bins_log2": 2, "dir_bins_log2": 3, "rough_thr": rough_thr,
+        "alpha_mode": alpha_mode, "alpha": alpha, "t_max": t_max,
+    }
+
+
+def tiny(alpha_mode=ALPHA_CONST, field=0, noise=1):
+    """64x64, 1 spp, 2 vertices/path in an open box with a sphere; diffuse;
+    2^16 slots; 8 iterations; constant alpha 0.2 (or Eq. 11 with T_max = 5)."""
+    cam = (0.5, 0.5, -1.5)
+    gen = {"width": 64, "height": 64, "spp": 1, "verts": 2, "seed": 1, "cam": cam,
+           "look": (0.0, 0.0, 1.0), "fov_y_deg": 40.0, "field": field, "noise": noise,
+           "field_scale": 1.0, "amp": (1.0, 0.8, 0.6), "glossy_lobe": 0}
+    return {"name": "tiny-64x64-2v", "scene": dict(kind=Scene.BOX, seed=1), "gen": gen,
+            "diffuse_only": True, "iterations": 8,
+            "table": _table(16, cam, 40.0, 64, 2.0, -6, alpha_mode=alpha_mode)}
+
+
+def plain():
+    """1280x720, 1 spp, 4 vertices/path; 64 random quads + 16 spheres with
+    roughness U[0.05, 1]; directional keys below roughness 0.3; 2^22 slots;
+    32 iterations; Eq. 11 with T_max = 5."""
+    cam = (0.0, 0.0, -10.0)
+    gen = {"width": 1280, "height": 720, "spp": 1, "verts": 4, "seed": 2, "cam": cam,
+           "look": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "field": 0, "noise": 1,
+           "field_scale": 4.0, "amp": (1.0, 0.8, 0.6), "glossy_lobe": 1}
+    return {"name": "plain-1280x720-4v", "scene": dict(kind=Scene.RANDOM, seed=2, glossy_frac=-1.0),
+            "gen": gen, "diffuse_only": False, "iterations": 32,
+            "table": _table(22, cam, 60.0, 720, 8.0 * math.sqrt(2.0), -5)}
+
+
+def precision():
+    """1920x1080, 1 spp, 5 vertices/path; half the primitives glossy; HDR
+    lognormal(0, 2) noise; 2^24 slots; 64 iterations."""
+    cam = (0.0, 0.0, -10.0)
+    gen = {"width": 1920, "height": 1080, "spp": 1, "verts": 5, "seed": 3, "cam": cam,
+           "look": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "field": 0, "noise": 2, "sigma": 2.0,
+           "field_scale": 4.0, "amp": (1.0, 0.8, 0.6), "glossy_lobe": 1}
+    return {"name": "precision-1920x1080-5v", "scene": dict(kind=Scene.RANDOM, seed=3, glossy_frac=0.5),
+            "gen": gen, "diffuse_only": False, "iterations": 64,
+            "table": _table(24, cam, 60.0, 1080, 4.0, -5)}
+
+
+BATCH_RES = ((256, 256), (512, 384), (640, 480), (1280, 720), (1920, 1080))
+
+
+def batched_sessions(n_sessions=16, seed=4):
+    """16 sessions of uneven resolutions, 1-4 spp, 3-5 vertices/path, tables of
+    2^18..2^23 slots, 32 iterations."""
+    from . import philox4x32_10
+    out = []
+    for i in range(n_sessions):
+        w, h = BATCH_RES[i % len(BATCH_RES)]
+        r = philox4x32_10((i, 0, 0, 0), (seed, 0x0b47c4ed))
+        spp = 1 + int(r[0] % 4)
+        verts = 3 + int(r[1] % 3)
+        n = w * h * spp * verts
+        log2 = int(min(23, max(18, math.ceil(math.log2(max(1, n))))))
+        cam = (0.0, 0.0, -10.0)
+        gen = {"width": w, "height": h, "spp": spp, "verts": verts, "seed": 100 + i, "cam": cam,
+               "look": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "field": 0, "noise": 1,
+               "field_scale": 4.0, "amp": (1.0, 0.8, 0.6), "glossy_lobe": 1}
+        out.append({"name": f"session{i}-{w}x{h}-{spp}spp-{verts}v",
+                    "scene": dict(kind=Scene.RANDOM, seed=100 + i, glossy_frac=-1.0),
+                    "gen": gen, "diffuse_only": False, "iterations": 32,
+                    "table": _table(log2, cam, 60.0, h, 4.0, -5)})
+    return out
+
+
+def records_per_iteration(wl) -> int:
+    g = wl["gen"]
+    return int(g["width"]) * int(g["height"]) * int(g.get("spp", 1)) * int(g["verts"])
+
+
+def make_scene(wl) -> Scene:
+    return Scene(**wl["scene"])

@@ -1,0 +1,48 @@
+"""Shared test helpers: fixture parsing and record construction (no method arithmetic)."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
+
+
+def golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            rows.append([c.strip() for c in line.split("|")])
+    return rows
+
+
+def records(n, **cols):
+    """Record dict of n entries; unspecified fields default to a +z normal,
+    +z direction, unit radiance and no roughness array."""
+    base = {"px": 0.0, "py": 0.0, "pz": 0.0, "nx": 0.0, "ny": 0.0, "nz": 1.0,
+            "ox": 0.0, "oy": 0.0, "oz": 1.0, "r": 1.0, "g": 1.0, "b": 1.0}
+    out = {}
+    for k in FIELDS:
+        v = cols.get(k, base.get(k))
+        if v is None:
+            out[k] = None
+            continue
+        a = np.asarray(v, dtype=np.float32)
+        out[k] = np.broadcast_to(a, (n,)).copy() if a.ndim == 0 else a.astype(np.float32)
+    return out
+
+
+def concat(recs):
+    out = {}
+    for k in FIELDS:
+        parts = [r[k] for r in recs]
+        out[k] = None if any(p is None for p in parts) else np.concatenate(parts)
+    return out
+
+
+def take(rec, idx):
+    return {k: (None if v is None else np.ascontiguousarray(v[idx])) for k, v in rec.items()}
