@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the PSTF hash path on one MI355X.
+
+One step is one whole iteration of the hot path on the plain workload
+(1280x720, 1 spp, 4 vertices per path = 3,686,400 vertex records; 2^22-slot
+table; Eq. 11 with T_max = 5): insert every record, apply the temporal blend,
+then query the approximant at every record (psf_iterate).  Inputs are
+synthetic (procedural scene generator, seeded) and resident in HBM before the
+timed region.  The JSON line carries the kernel-level roofline of the
+dominant kernel (HIP events on the library's stream) and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+REC_BYTES = 52         # position, normal, direction, rgb, roughness (f32)
+QRY_BYTES = 40 + 12    # query fields in, rgb out
+CELL_INSERT, CELL_UPDATE, CELL_QUERY = 40, 64, 24
+
+
+def _workload(name):
+    from synth import workloads as W
+    return {"plain": W.plain, "tiny": W.tiny, "precision": W.precision}[name]()
+
+
+def algorithmic_bytes(n, c):
+    """Bytes the method must move per iteration for n records (queries = n)
+    touching c distinct cells, split by kernel kind."""
+    return {
+        "bin": n * REC_BYTES,
+        "merge_blend": c * (CELL_INSERT + CELL_UPDATE),
+        "query": n * QRY_BYTES + c * CELL_QUERY,
+        "iteration": n * (REC_BYTES + QRY_BYTES) + c * (CELL_INSERT + CELL_UPDATE + CELL_QUERY),
+    }
+
+
+def cpu_baseline(wl, rec, budget_s):
+    """The oracle as it stands, single-threaded, on whole iterations of the
+    same records until the time budget is used (at least one iteration)."""
+    import oracle
+    n = len(rec["px"])
+    orc = oracle.Oracle(**wl["table"])
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        orc.insert(rec)
+        orc.update()
+        orc.query(rec)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+        if el / done * (done + 1) > budget_s * 1.5:
+            break
+    return {"value": n * done / el, "unit": "vertex records/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} whole iteration(s) (insert+update+query) of {n} records of the "
+                      f"{wl['name']} workload, single thread, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="plain", choices=["plain", "tiny", "precision"])
+    ap.add_argument("--pool", type=int, default=8, help="distinct iteration buffers, cycled")
+    ap.add_argument("--insert-mode", type=int, default=0)
+    ap.add_argument("--split", action="store_true", help="separate insert/update/query calls")
+    ap.add_argument("--state", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the hash path is "
+                                   "measured on a single MI355X (--gpus 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2005_07547_amd import psf
+    from synth import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = _workload(args.workload)
+    sc = W.make_scene(wl)
+    n = W.records_per_iteration(wl)
+    pool = max(1, min(args.pool, args.warmup + args.steps))
+    host = []
+    bufs = []
+    for i in range(pool):
+        rec = sc.generate(wl["gen"], i)
+        if wl["diffuse_only"]:
+            rec = dict(rec)
+            rec["rough"] = None
+        host.append(rec)
+        bufs.append({k: (None if v is None else torch.from_numpy(v).to(dev)) for k, v in rec.items()})
+    out = torch.empty((3, n), dtype=torch.float32, device=dev)
+    found = torch.empty(n, dtype=torch.uint8, device=dev)
+    dtype_code = {"f32": psf.PSF_STATE_F32, "f16": psf.PSF_STATE_F16, "bf16": psf.PSF_STATE_BF16}[args.state]
+    flags = 0 if args.no_timing else psf.PSF_FLAG_TIMING
+    table = psf.Table(**dict(wl["table"], insert_mode=args.insert_mode, state_dtype=dtype_code,
+                             flags=flags, max_batch=max(n, 1)))
+    torch.cuda.synchronize()
+
+    def step(i):
+        b = bufs[i % pool]
+        if args.split:
+            table.insert(b)
+            table.update()
+            table.query(b, out=out, found=found)
+        else:
+            table.iterate(b, out=out, found=found)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if flags:
+        table.kernel_times(reset=True)
+    st0 = table.stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step(args.warmup + k)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    iter_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    st1 = table.stats()
+    kt = table.kernel_times() if flags else {}
+    steps = args.steps
+    touched = (st1["touched_total"] - st0["touched_total"]) / max(1, st1["updates"] - st0["updates"])
+    ab = algorithmic_bytes(n, touched)
+    kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])} for k, v in kt.items()}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        per_launch = ab.get(dom)
+        if per_launch is None:  # split mode kernels: attribute the insert bytes
+            per_launch = {"merge": touched * CELL_INSERT, "update": touched * CELL_UPDATE,
+                          "insert_direct": n * REC_BYTES + touched * CELL_INSERT}.get(dom, 0)
+        ach = per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "algorithmic_bytes_per_launch": int(per_launch)}
+    iter_gbs = ab["iteration"] / (elapsed / steps) / 1e9
+    result = {
+        "metric": "vertex records/s (insert+temporal update+query)",
+        "value": round(n * steps / elapsed, 1),
+        "unit": "vertex records/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.state == "f32" else f"f32 accumulate, {args.state} state",
+        "data": "synthetic (seeded procedural scene, records resident in HBM)",
+        "config": {"workload": wl["name"], "records_per_iteration": n,
+                   "log2_slots": wl["table"]["log2_slots"], "iterations_timed": steps,
+                   "mode": "split" if args.split else "psf_iterate",
+                   "insert_mode": args.insert_mode, "pool_buffers": pool},
+        "p50_iter_ms": round(float(np.percentile(iter_ms, 50)), 4),
+        "p99_iter_ms": round(float(np.percentile(iter_ms, 99)), 4),
+        "iteration_hbm_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
+        "cells_touched_per_iteration": int(touched),
+        "occupancy": round(st1["occupied"] / (1 << wl["table"]["log2_slots"]), 4),
+        "dropped": st1["dropped"],
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl, host[0], args.cpu_seconds)
+    table.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

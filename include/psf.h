@@ -1,0 +1,269 @@
+/*
+ * psf.h -- C ABI of the progressive spatio-temporal filtering (PSTF) hash
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: J. Pantaleoni, "Online path sampling control with progressive
+ * spatio-temporal filtering", arXiv 2005.07547.  Each frame (iteration) the
+ * caller
+ *   1. inserts path-vertex samples into a spatio-directional hash table
+ *      (Sec. 2.6): every cell accumulates a sample count and a sum of sample
+ *      values, the counter c_h^new and the numerator of Eq. 6 with box basis
+ *      functions and MIS weight 1 (Algorithm 1: increment_counters,
+ *      update_approx);
+ *   2. applies the temporal blend of Sec. 2.4 (Eq. 10-11) to every cell that
+ *      received samples: L <- (1 - alpha) L + alpha * mean, with
+ *      alpha = max(sqrt(c_new / (c_old + c_new)), 1 / T_max) and the
+ *      cumulative count c_old += c_new;
+ *   3. queries the filtered approximant at arbitrary vertices (the lookup of
+ *      L~^old inside Algorithm 1 and the control-variate term of Eq. 25).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* (and the arrays inside psf_records / psf_queries)
+ *     are DEVICE pointers; everything else is host memory.
+ *   - stream is a hipStream_t (0 = the null stream).  Work is enqueued on it
+ *     asynchronously unless a function says it synchronises.  A table is
+ *     used from one stream at a time; the caller orders its calls.
+ *   - Every call returns a psf_status.  Argument errors return before any
+ *     work is enqueued; psf_last_error() then describes the problem (a
+ *     thread-local string owned by the library).  Kernel launch failures
+ *     return PSF_HIP_ERROR; asynchronous device faults surface at the
+ *     caller's next synchronisation.
+ *   - Data conditions are not errors: non-finite inputs are counted as
+ *     skipped, samples for which no slot was found within max_probe probes
+ *     (table full) as dropped, and grid coordinates outside the signed
+ *     16-bit range as coord_overflow (their key wraps).  See psf_get_stats.
+ *   - n = 0 is a no-op that returns PSF_OK.
+ */
+#ifndef PSF_H_
+#define PSF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* psf_stream;  /* a hipStream_t */
+
+typedef enum psf_status {
+  PSF_OK = 0,
+  PSF_INVALID_ARGUMENT = 1,
+  PSF_OUT_OF_MEMORY = 2,
+  PSF_BUFFER_TOO_SMALL = 3,
+  PSF_HIP_ERROR = 4,
+  PSF_NOT_SUPPORTED = 5
+} psf_status;
+
+/* Temporal blend modes (Sec. 2.4).  PAPER is Eq. 11.  CONST is the
+ * constant-alpha "exponential weighting" limit and LINEAR the "linear
+ * accumulation" limit (no square root) that the same section names.  In
+ * every mode a cell blended for the first time (c_old = 0) takes its mean. */
+enum { PSF_ALPHA_PAPER = 0, PSF_ALPHA_CONST = 1, PSF_ALPHA_LINEAR = 2 };
+
+/* Storage of the approximant.  The blend always runs in FP32 and the
+ * accumulators are FP32; F16 and BF16 round to nearest even on store (F16
+ * saturates at +-65504 and counts each saturation). */
+enum { PSF_STATE_F32 = 0, PSF_STATE_F16 = 1, PSF_STATE_BF16 = 2 };
+
+/* psf_reset what-bits.  COUNTERS zeroes every cell's c_old (the global
+ * counter reset of Sec. 2.4): cells keep their key but are not reported by
+ * queries until blended again, and their next blend starts over with
+ * alpha = 1.  CLEAR empties the table.  STATS zeroes the statistics. */
+enum { PSF_RESET_COUNTERS = 1u, PSF_RESET_CLEAR = 2u, PSF_RESET_STATS = 4u };
+
+/* Insert strategies (psf_config.insert_mode). */
+enum {
+  PSF_INSERT_AUTO = 0,        /* library choice */
+  PSF_INSERT_DIRECT = 1,      /* wave-merged global CAS/atomics per record */
+  PSF_INSERT_PARTITIONED = 2  /* bin by table partition, aggregate in LDS */
+};
+
+/* psf_config.flags */
+enum {
+  PSF_FLAG_PROBE_STATS = 1u, /* record a probe-length histogram */
+  PSF_FLAG_TIMING = 2u       /* bracket every kernel launch with HIP events */
+};
+
+/* Kernel kinds reported by psf_kernel_times. */
+enum {
+  PSF_K_KEYS = 0,
+  PSF_K_INSERT_DIRECT = 1,
+  PSF_K_BIN = 2,
+  PSF_K_MERGE = 3,
+  PSF_K_MERGE_BLEND = 4,
+  PSF_K_UPDATE = 5,
+  PSF_K_QUERY = 6,
+  PSF_K_BATCH = 7,
+  PSF_K_COUNT = 8
+};
+
+/*
+ * Table configuration.  The cell key (spatio-directional hashing, Sec. 2.6;
+ * this library's fixed specification, identical on every implementation):
+ *   level  l = clamp(floor(e / 2), 0, max_level), e the binary32 exponent of
+ *             kappa * |p - cam|^2 (no square root or logarithm; kappa = 0
+ *             selects l = 0).  With kappa = (k_s * theta_pixel / 2^e_min)^2
+ *             the cell edge 2^(e_min + l) tracks k_s pixel footprints at the
+ *             vertex's camera distance (the level hierarchy of Sec. 2.3).
+ *   coords (ix, iy, iz) = floor(p * 2^-(e_min + l)), kept modulo 2^16.
+ *   normal octahedral bin on a 2^normal_bins_log2 square grid.
+ *   glossy vertices (roughness array given and roughness < rough_thr, strict)
+ *             also key the outgoing direction on a 2^dir_bins_log2 grid.
+ *   key = l<<59 | glossy<<58 | dir_bin<<52 | normal_bin<<48 | iz<<32 | iy<<16 | ix
+ * Bit 63 of a key is always 0; the key is injective on cells while no
+ * coordinate overflows, so the stored key is its own checksum.
+ */
+typedef struct psf_config {
+  uint32_t log2_slots;       /* 4..30: table of 2^log2_slots slots */
+  uint32_t max_probe;        /* 1..2^log2_slots: linear-probe bound */
+  float cam[3];              /* camera position for the level rule */
+  float kappa;               /* >= 0, finite; 0 = fixed level 0 */
+  int32_t e_min;             /* finest cell edge 2^e_min, -100..100 */
+  int32_t max_level;         /* 0..15 */
+  int32_t normal_bins_log2;  /* 0..2 */
+  int32_t dir_bins_log2;     /* 0..3 */
+  float rough_thr;           /* glossy iff roughness < rough_thr */
+  int32_t alpha_mode;        /* PSF_ALPHA_* */
+  float alpha;               /* CONST mode alpha, (0, 1] */
+  float t_max;               /* PAPER mode temporal window, >= 1 */
+  int32_t state_dtype;       /* PSF_STATE_* */
+  uint32_t flags;            /* PSF_FLAG_* */
+  int32_t insert_mode;       /* PSF_INSERT_* */
+  uint32_t part_log2;        /* partitioned insert: log2 slots per partition
+                                (0 = default 11, else 8..12) */
+  uint64_t max_batch;        /* partitioned insert: records binned per launch
+                                (0 = default 4M); larger inserts are split */
+} psf_config;
+
+/* Vertex records, structure of arrays, N float32 each (device memory).
+ * ox..oz is the outgoing direction omega_o (pointing back along the path,
+ * Algorithm 1); it is read only for glossy vertices.  rough may be NULL
+ * (every vertex diffuse).  r, g, b is the sample value assembled by the
+ * caller (the path tail estimate of Eq. 3 / Eq. 9). */
+typedef struct psf_records {
+  const float *px, *py, *pz;
+  const float *nx, *ny, *nz;
+  const float *ox, *oy, *oz;
+  const float *r, *g, *b;
+  const float *rough;
+} psf_records;
+
+/* Query vertices: the same fields without a sample value. */
+typedef struct psf_queries {
+  const float *px, *py, *pz;
+  const float *nx, *ny, *nz;
+  const float *ox, *oy, *oz;
+  const float *rough;
+} psf_queries;
+
+typedef struct psf_stats {
+  uint64_t submitted;       /* records passed to insert calls */
+  uint64_t skipped;         /* non-finite records (inserts and queries are
+                               counted separately: this is inserts) */
+  uint64_t dropped;         /* records with no slot within max_probe */
+  uint64_t coord_overflow;  /* inserted records with a wrapped coordinate */
+  uint64_t touched_last;    /* cells blended by the last temporal update */
+  uint64_t touched_total;   /* cells blended, summed over updates */
+  uint64_t updates;         /* temporal updates applied */
+  uint64_t saturated;       /* F16 stores clamped to +-65504 */
+  uint64_t occupied;        /* non-empty slots (computed on request) */
+  uint64_t probe_hist[16];  /* with PSF_FLAG_PROBE_STATS: probes needed per
+                               cell insertion, bucket min(probes-1, 15) */
+} psf_stats;
+
+typedef struct psf_table psf_table;
+
+/* Bytes of device memory a table with this configuration needs (slots,
+ * accumulators, touched list, staging, statistics).  0 if cfg is invalid. */
+size_t psf_table_bytes(const psf_config* cfg);
+
+/* Create a table.  device_buffer (nullable) is caller-owned device memory of
+ * at least psf_table_bytes(cfg) bytes, 256-byte aligned, that must outlive
+ * the table; when NULL the library allocates.  The table is initialised
+ * (all slots empty) on stream.  BUFFER_TOO_SMALL if buffer_bytes is short. */
+psf_status psf_create_table(const psf_config* cfg, void* device_buffer, size_t buffer_bytes,
+                            psf_stream stream, psf_table** out);
+
+/* Synchronises the table's last stream and frees what the library
+ * allocated.  NULL is a no-op. */
+psf_status psf_destroy(psf_table* t);
+
+/* Scatter n records into the table (Eq. 5-6 accumulation; Algorithm 1's
+ * increment_counters / update_approx).  May be called several times before
+ * a temporal update; contributions add up. */
+psf_status psf_insert_samples(psf_table* t, const psf_records* rec, uint64_t n, psf_stream stream);
+
+/* Fold every touched cell's mean into its approximant (Eq. 10-11), add its
+ * count to c_old and clear its accumulator.  Untouched cells are unchanged. */
+psf_status psf_temporal_update(psf_table* t, psf_stream stream);
+
+/* Look up n query vertices.  d_out_rgb receives 3*n floats, SoA (all r, then
+ * all g, then all b); d_out_found (nullable) receives n bytes, 1 where the
+ * query's cell exists and has been blended (c_old > 0), else 0 with a zero
+ * output.  Reads the state left by the last completed temporal update. */
+psf_status psf_query(psf_table* t, const psf_queries* q, uint64_t n, float* d_out_rgb,
+                     uint8_t* d_out_found, psf_stream stream);
+
+/* One whole iteration: insert rec, temporal update, then query q.  Same
+ * result as the three calls in sequence; when the table has no pending
+ * inserts the partitioned strategy fuses insert and blend in one pass. */
+psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const psf_queries* q,
+                       uint64_t nq, float* d_out_rgb, uint8_t* d_out_found, psf_stream stream);
+
+/* Reset (PSF_RESET_* bits). */
+psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream);
+
+/* Keys of n records (all ones for rejected records); test support. */
+psf_status psf_compute_keys(psf_table* t, const psf_records* rec, uint64_t n, uint64_t* d_out_keys,
+                            psf_stream stream);
+
+/* Statistics into *out (host).  Synchronises stream. */
+psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream);
+
+/* Copy every occupied cell to host arrays of capacity cap: keys, pending
+ * counts n_new, cumulative counts c_old, approximant (3*cap floats, SoA,
+ * decoded to float).  Any output pointer except keys may be NULL.  *count
+ * receives the number of occupied cells; BUFFER_TOO_SMALL if it exceeds cap
+ * (nothing is written then).  Order is unspecified.  Synchronises stream. */
+psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
+                            float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
+
+/* Batched form: one iteration (insert, update, query) of k independent
+ * sessions in a single persistent launch.  Each session's result equals
+ * the same session run alone. */
+typedef struct psf_session {
+  psf_table* table;
+  psf_records rec;
+  uint64_t n;
+  psf_queries q;
+  uint64_t nq;
+  float* d_out_rgb;
+  uint8_t* d_out_found;
+} psf_session;
+
+psf_status psf_iterate_batch(const psf_session* sessions, uint32_t k, psf_stream stream);
+
+/* Per-kernel timing (tables created with PSF_FLAG_TIMING): for each kernel
+ * kind k < PSF_K_COUNT, launches[k] and total_ms[k] (host arrays of
+ * PSF_K_COUNT entries) receive the launches recorded since the last reset
+ * and their summed HIP-event durations, measured on the stream each kernel
+ * ran on.  reset != 0 clears the record.  Synchronises the recorded events.
+ * At most 8192 launches are kept; older ones are folded into the sums as
+ * the ring wraps.  NOT_SUPPORTED without PSF_FLAG_TIMING. */
+psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* total_ms, int reset);
+
+/* Name of kernel kind k ("" if out of range). */
+const char* psf_kernel_name(uint32_t k);
+
+/* Description of the last error on this thread ("" if none). */
+const char* psf_last_error(void);
+
+/* Library version string. */
+const char* psf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSF_H_ */

@@ -32,8 +32,8 @@ class _Records(ctypes.Structure):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (no GPU code involved)."""
-    from . import build as _b
-    return _b.build(force=force)
+    import importlib
+    return importlib.import_module(__name__ + ".build").build(force=force)
 
 
 def _load():

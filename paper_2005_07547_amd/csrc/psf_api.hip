@@ -1,0 +1,567 @@
+// C-ABI layer of the PSTF hash library: argument validation, memory layout,
+// strategy selection and kernel launches.  Nothing here throws across the
+// ABI; every entry point returns a psf_status.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psf.h"
+#include "psf_internal.h"
+
+#define PSF_API extern "C" __attribute__((visibility("default")))
+
+// Ring of HIP-event pairs bracketing kernel launches (PSF_FLAG_TIMING).
+struct KernelTimer {
+  static constexpr uint32_t kCap = 4096;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  std::vector<uint8_t> kind;
+  uint32_t next = 0, used = 0;
+  uint64_t launches[PSF_K_COUNT] = {};
+  double total_ms[PSF_K_COUNT] = {};
+
+  hipError_t init() {
+    ev.assign(2 * kCap, nullptr);
+    kind.assign(kCap, 0);
+    for (auto& e : ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  void destroy() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+  hipError_t fold(uint32_t i) {
+    hipError_t r = hipEventSynchronize(ev[2 * i + 1]);
+    float ms = 0.0f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+    if (r != hipSuccess) return r;
+    launches[kind[i]] += 1;
+    total_ms[kind[i]] += ms;
+    return hipSuccess;
+  }
+  hipError_t flush() {
+    const uint32_t first = (next + kCap - used) % kCap;
+    for (uint32_t j = 0; j < used; ++j) {
+      hipError_t r = fold((first + j) % kCap);
+      if (r != hipSuccess) return r;
+    }
+    used = 0;
+    return hipSuccess;
+  }
+};
+
+struct psf_table {
+  psf_config cfg;
+  KernelTimer* timer = nullptr;
+  void* base = nullptr;
+  size_t bytes = 0;
+  bool owns = false;
+  psf::TableView tv{};
+  psf::KeyParams kp{};
+  psf::BlendParams bp{};
+  psf::PartView pv{};
+  bool partitioned = false;  // strategy used by inserts
+  uint64_t submitted = 0;
+  bool pending = false;      // accumulators hold samples not yet blended
+  hipStream_t last = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+psf_status fail(psf_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+psf_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return PSF_HIP_ERROR;
+}
+
+// Run one kernel launch, bracketed by events when the table records timing.
+template <class F>
+hipError_t timed(psf_table* t, int kind, hipStream_t s, F&& launch) {
+  KernelTimer* tm = t->timer;
+  if (!tm) return launch();
+  const uint32_t i = tm->next;
+  if (tm->used == KernelTimer::kCap) {
+    hipError_t r = tm->fold(i);
+    if (r != hipSuccess) return r;
+    tm->used--;
+  }
+  hipError_t r = hipEventRecord(tm->ev[2 * i], s);
+  if (r != hipSuccess) return r;
+  r = launch();
+  if (r != hipSuccess) return r;
+  r = hipEventRecord(tm->ev[2 * i + 1], s);
+  if (r != hipSuccess) return r;
+  tm->kind[i] = (uint8_t)kind;
+  tm->next = (i + 1) % KernelTimer::kCap;
+  tm->used++;
+  return hipSuccess;
+}
+
+constexpr uint32_t kDefaultPartLog2 = 11;
+constexpr uint64_t kDefaultBatch = 1ull << 22;
+constexpr uint32_t kTile = 8192;          // records per binning tile
+constexpr uint32_t kMaxPartitions = 1u << 13;  // LDS histogram of the binning pass
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool validate(const psf_config* c, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return false;
+  };
+  if (!c) return bad("config is NULL");
+  if (c->log2_slots < 4 || c->log2_slots > 30) return bad("log2_slots must be in [4, 30]");
+  if (c->max_probe < 1 || (uint64_t)c->max_probe > (1ull << c->log2_slots))
+    return bad("max_probe must be in [1, 2^log2_slots]");
+  if (!std::isfinite(c->cam[0]) || !std::isfinite(c->cam[1]) || !std::isfinite(c->cam[2]))
+    return bad("cam must be finite");
+  if (!std::isfinite(c->kappa) || c->kappa < 0.0f) return bad("kappa must be finite and >= 0");
+  if (c->e_min < -100 || c->e_min > 100) return bad("e_min must be in [-100, 100]");
+  if (c->max_level < 0 || c->max_level > 15) return bad("max_level must be in [0, 15]");
+  if (c->normal_bins_log2 < 0 || c->normal_bins_log2 > 2) return bad("normal_bins_log2 must be in [0, 2]");
+  if (c->dir_bins_log2 < 0 || c->dir_bins_log2 > 3) return bad("dir_bins_log2 must be in [0, 3]");
+  if (std::isnan(c->rough_thr)) return bad("rough_thr is NaN");
+  if (c->alpha_mode < 0 || c->alpha_mode > 2) return bad("alpha_mode must be PAPER, CONST or LINEAR");
+  if (c->alpha_mode == PSF_ALPHA_CONST && !(c->alpha > 0.0f && c->alpha <= 1.0f))
+    return bad("alpha must be in (0, 1]");
+  if (c->alpha_mode == PSF_ALPHA_PAPER && !(std::isfinite(c->t_max) && c->t_max >= 1.0f))
+    return bad("t_max must be finite and >= 1");
+  if (c->state_dtype < 0 || c->state_dtype > 2) return bad("state_dtype must be F32, F16 or BF16");
+  if (c->insert_mode < 0 || c->insert_mode > 2) return bad("insert_mode must be AUTO, DIRECT or PARTITIONED");
+  if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
+  if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING)) return bad("unknown flags");
+  if (c->max_batch > (1ull << 32)) return bad("max_batch must be <= 2^32");
+  return true;
+}
+
+struct Layout {
+  size_t stats = 0, slots = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0, total = 0;
+  uint32_t part_log2 = 0;
+  bool part = false;
+  uint64_t cap = 0;
+  uint32_t tiles = 0;
+};
+
+Layout layout_of(const psf_config& c) {
+  Layout L;
+  const uint64_t S = 1ull << c.log2_slots;
+  L.part_log2 = c.part_log2 ? c.part_log2 : kDefaultPartLog2;
+  if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;
+  const uint64_t P = 1ull << (c.log2_slots - L.part_log2);
+  L.part = c.insert_mode != PSF_INSERT_DIRECT && P <= kMaxPartitions;
+  size_t off = 0;
+  L.stats = off;
+  off = align_up(off + sizeof(psf::DevStats), 256);
+  L.slots = off;
+  off = align_up(off + S * sizeof(psf::Slot), 256);
+  L.acc = off;
+  off = align_up(off + S * sizeof(psf::Acc), 256);
+  if (L.part) {
+    L.cap = c.max_batch ? c.max_batch : kDefaultBatch;
+    L.tiles = (uint32_t)((L.cap + kTile - 1) / kTile);
+    L.cap = (uint64_t)L.tiles * kTile;
+    L.stage_key = off;
+    off = align_up(off + L.cap * 8, 256);
+    L.stage_rgb = off;
+    off = align_up(off + L.cap * 12, 256);
+    L.runs = off;
+    off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
+  }
+  L.total = off;
+  return L;
+}
+
+bool rec_ok(const psf_records* r, std::string* why) {
+  if (!r) return (*why = "records is NULL", false);
+  if (!r->px || !r->py || !r->pz || !r->nx || !r->ny || !r->nz)
+    return (*why = "position and normal arrays are required", false);
+  if (!r->r || !r->g || !r->b) return (*why = "r, g, b arrays are required", false);
+  if (r->rough && (!r->ox || !r->oy || !r->oz))
+    return (*why = "direction arrays are required when roughness is given", false);
+  return true;
+}
+
+bool qry_ok(const psf_queries* q, std::string* why) {
+  if (!q) return (*why = "queries is NULL", false);
+  if (!q->px || !q->py || !q->pz || !q->nx || !q->ny || !q->nz)
+    return (*why = "position and normal arrays are required", false);
+  if (q->rough && (!q->ox || !q->oy || !q->oz))
+    return (*why = "direction arrays are required when roughness is given", false);
+  return true;
+}
+
+psf::RecPtrs rec_ptrs(const psf_records* r) {
+  return psf::RecPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz,
+                      r->r,  r->g,  r->b,  r->rough};
+}
+
+psf::QryPtrs qry_ptrs(const psf_queries* q) {
+  return psf::QryPtrs{q->px, q->py, q->pz, q->nx, q->ny, q->nz, q->ox, q->oy, q->oz, q->rough};
+}
+
+psf::QryPtrs qry_from_rec(const psf_records* r) {
+  return psf::QryPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz, r->rough};
+}
+
+uint64_t nslots(const psf_table* t) { return 1ull << t->cfg.log2_slots; }
+
+psf::RecPtrs offset_rec(const psf::RecPtrs& rp, uint64_t off) {
+  psf::RecPtrs sub = rp;
+  const float** f[] = {&sub.px, &sub.py, &sub.pz, &sub.nx, &sub.ny, &sub.nz, &sub.ox,
+                       &sub.oy, &sub.oz, &sub.r,  &sub.g,  &sub.b,  &sub.rough};
+  for (auto* p : f)
+    if (*p) *p += off;
+  return sub;
+}
+
+psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream_t s) {
+  hipError_t e;
+  if (t->partitioned) {
+    for (uint64_t off = 0; off < n; off += t->pv.capacity) {
+      const uint64_t m = (n - off < t->pv.capacity) ? n - off : t->pv.capacity;
+      const psf::RecPtrs sub = offset_rec(rp, off);
+      e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(sub, m, t->kp, t->tv, t->pv, s); });
+      if (e == hipSuccess)
+        e = timed(t, PSF_K_MERGE, s, [&] { return psf::launch_merge(m, t->tv, t->pv, nullptr, s); });
+      if (e != hipSuccess) return hip_fail(e, "partitioned insert launch");
+    }
+  } else {
+    e = timed(t, PSF_K_INSERT_DIRECT, s,
+              [&] { return psf::launch_insert_direct(rp, n, t->kp, t->tv, s); });
+    if (e != hipSuccess) return hip_fail(e, "insert launch");
+  }
+  t->pending = true;
+  t->submitted += n;
+  return PSF_OK;
+}
+
+psf_status do_update(psf_table* t, hipStream_t s) {
+  hipError_t e = timed(t, PSF_K_UPDATE, s, [&] { return psf::launch_update(t->tv, t->bp, nslots(t), s); });
+  if (e != hipSuccess) return hip_fail(e, "update launch");
+  t->pending = false;
+  return PSF_OK;
+}
+
+psf_status do_query(psf_table* t, const psf::QryPtrs& q, uint64_t n, float* out, uint8_t* found,
+                    hipStream_t s) {
+  hipError_t e = timed(t, PSF_K_QUERY, s, [&] {
+    return psf::launch_query(q, n, t->kp, t->tv, t->cfg.state_dtype, out, found, s);
+  });
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
+}
+
+}  // namespace
+
+PSF_API size_t psf_table_bytes(const psf_config* cfg) {
+  std::string why;
+  if (!validate(cfg, &why)) {
+    g_err = why;
+    return 0;
+  }
+  return layout_of(*cfg).total;
+}
+
+PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, size_t buffer_bytes,
+                                    psf_stream stream, psf_table** out) {
+  std::string why;
+  if (!out) return fail(PSF_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!validate(cfg, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  const Layout L = layout_of(*cfg);
+  if (device_buffer) {
+    if (buffer_bytes < L.total)
+      return fail(PSF_BUFFER_TOO_SMALL, "device buffer smaller than psf_table_bytes(cfg)");
+    if (reinterpret_cast<uintptr_t>(device_buffer) % 256 != 0)
+      return fail(PSF_INVALID_ARGUMENT, "device buffer must be 256-byte aligned");
+  }
+  psf_table* t = new (std::nothrow) psf_table();
+  if (!t) return fail(PSF_OUT_OF_MEMORY, "host allocation failed");
+  t->cfg = *cfg;
+  t->bytes = L.total;
+  if (device_buffer) {
+    t->base = device_buffer;
+  } else {
+    hipError_t e = hipMalloc(&t->base, L.total);
+    if (e != hipSuccess) {
+      delete t;
+      (void)hipGetLastError();
+      return fail(PSF_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    t->owns = true;
+  }
+  char* b = static_cast<char*>(t->base);
+  t->tv.stats = reinterpret_cast<psf::DevStats*>(b + L.stats);
+  t->tv.slots = reinterpret_cast<psf::Slot*>(b + L.slots);
+  t->tv.acc = reinterpret_cast<psf::Acc*>(b + L.acc);
+  t->tv.log2_slots = cfg->log2_slots;
+  t->tv.part_log2 = L.part_log2;
+  t->tv.max_probe = cfg->max_probe < (1u << L.part_log2) ? cfg->max_probe : (1u << L.part_log2);
+  t->tv.flags = cfg->flags;
+  t->kp = psf::KeyParams{cfg->cam[0], cfg->cam[1], cfg->cam[2], cfg->kappa, cfg->e_min,
+                         cfg->max_level, cfg->normal_bins_log2, cfg->dir_bins_log2, cfg->rough_thr};
+  t->bp = psf::BlendParams{cfg->alpha_mode, cfg->alpha, 1.0f / cfg->t_max, cfg->state_dtype};
+  if (cfg->alpha_mode != PSF_ALPHA_PAPER) t->bp.inv_t_max = 0.0f;
+  if (L.part) {
+    t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
+    t->pv.stage_rgb = reinterpret_cast<float*>(b + L.stage_rgb);
+    t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
+    t->pv.tile = kTile;
+    t->pv.max_tiles = L.tiles;
+    t->pv.capacity = L.cap;
+    t->partitioned = true;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (cfg->flags & PSF_FLAG_TIMING) {
+    t->timer = new (std::nothrow) KernelTimer();
+    e = t->timer ? t->timer->init() : hipErrorOutOfMemory;
+  }
+  if (e == hipSuccess) e = psf::launch_zero(t->tv.stats, sizeof(psf::DevStats), s);
+  if (e == hipSuccess) e = psf::launch_clear(t->tv, nslots(t), s);
+  if (e != hipSuccess) {
+    if (t->timer) {
+      t->timer->destroy();
+      delete t->timer;
+    }
+    if (t->owns) (void)hipFree(t->base);
+    delete t;
+    return hip_fail(e, "table initialisation");
+  }
+  t->last = s;
+  *out = t;
+  return PSF_OK;
+}
+
+PSF_API psf_status psf_destroy(psf_table* t) {
+  if (!t) return PSF_OK;
+  hipError_t e = hipStreamSynchronize(t->last);
+  hipError_t f = hipSuccess;
+  if (t->owns) f = hipFree(t->base);
+  if (t->timer) {
+    t->timer->destroy();
+    delete t->timer;
+  }
+  delete t;
+  if (e != hipSuccess) return hip_fail(e, "synchronise before destroy");
+  if (f != hipSuccess) return hip_fail(f, "hipFree");
+  return PSF_OK;
+}
+
+PSF_API psf_status psf_insert_samples(psf_table* t, const psf_records* rec, uint64_t n,
+                                      psf_stream stream) {
+  std::string why;
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!rec_ok(rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  return do_insert(t, rec_ptrs(rec), n, s);
+}
+
+PSF_API psf_status psf_temporal_update(psf_table* t, psf_stream stream) {
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  return do_update(t, s);
+}
+
+PSF_API psf_status psf_query(psf_table* t, const psf_queries* q, uint64_t n, float* d_out_rgb,
+                             uint8_t* d_out_found, psf_stream stream) {
+  std::string why;
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!qry_ok(q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (!d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  return do_query(t, qry_ptrs(q), n, d_out_rgb, d_out_found, s);
+}
+
+PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const psf_queries* q,
+                               uint64_t nq, float* d_out_rgb, uint8_t* d_out_found, psf_stream stream) {
+  std::string why;
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n > 0 && !rec_ok(rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (nq > 0 && !qry_ok(q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (nq > 0 && !d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  psf_status st = PSF_OK;
+  if (n > 0 && t->partitioned && !t->pending && n <= t->pv.capacity) {
+    const psf::RecPtrs rp = rec_ptrs(rec);
+    hipError_t e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(rp, n, t->kp, t->tv, t->pv, s); });
+    if (e == hipSuccess)
+      e = timed(t, PSF_K_MERGE_BLEND, s, [&] { return psf::launch_merge(n, t->tv, t->pv, &t->bp, s); });
+    if (e != hipSuccess) return hip_fail(e, "fused insert launch");
+    t->submitted += n;
+  } else {
+    if (n > 0) st = do_insert(t, rec_ptrs(rec), n, s);
+    if (st == PSF_OK) st = do_update(t, s);
+  }
+  if (st != PSF_OK || nq == 0) return st;
+  return do_query(t, qry_ptrs(q), nq, d_out_rgb, d_out_found, s);
+}
+
+PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (what & ~(uint32_t)(PSF_RESET_COUNTERS | PSF_RESET_CLEAR | PSF_RESET_STATS))
+    return fail(PSF_INVALID_ARGUMENT, "unknown reset bits");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  hipError_t e = hipSuccess;
+  if (what & PSF_RESET_CLEAR) {
+    e = psf::launch_clear(t->tv, nslots(t), s);
+    t->pending = false;
+  } else if (what & PSF_RESET_COUNTERS) {
+    e = psf::launch_reset_counters(t->tv, nslots(t), s);
+  }
+  if (e == hipSuccess && (what & PSF_RESET_STATS)) {
+    e = psf::launch_zero(t->tv.stats, sizeof(psf::DevStats), s);
+    t->submitted = 0;
+  }
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
+}
+
+PSF_API psf_status psf_compute_keys(psf_table* t, const psf_records* rec, uint64_t n,
+                                    uint64_t* d_out_keys, psf_stream stream) {
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!rec || !rec->px || !rec->py || !rec->pz || !rec->nx || !rec->ny || !rec->nz ||
+      (rec->rough && (!rec->ox || !rec->oy || !rec->oz)))
+    return fail(PSF_INVALID_ARGUMENT, "position, normal (and direction with roughness) arrays are required");
+  if (!d_out_keys) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  hipError_t e = timed(t, PSF_K_KEYS, s, [&] {
+    return psf::launch_keys(rec_ptrs(rec), n, t->kp, reinterpret_cast<unsigned long long*>(d_out_keys), s);
+  });
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "keys launch");
+}
+
+namespace {
+psf_status count_occupied(psf_table* t, hipStream_t s, uint64_t* out) {
+  unsigned long long* d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(unsigned long long));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  e = hipMemsetAsync(d, 0, sizeof(unsigned long long), s);
+  if (e == hipSuccess) e = psf::launch_count_occupied(t->tv, nslots(t), d, s);
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "count occupied");
+  *out = h;
+  return PSF_OK;
+}
+}  // namespace
+
+PSF_API psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream) {
+  if (!t || !out) return fail(PSF_INVALID_ARGUMENT, "table or output is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  psf::DevStats d;
+  hipError_t e = hipMemcpyAsync(&d, t->tv.stats, sizeof d, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "read statistics");
+  uint64_t occ = 0;
+  psf_status st = count_occupied(t, s, &occ);
+  if (st != PSF_OK) return st;
+  std::memset(out, 0, sizeof *out);
+  out->submitted = t->submitted;
+  out->skipped = d.skipped;
+  out->dropped = d.dropped;
+  out->coord_overflow = d.coord_overflow;
+  out->touched_last = d.touched_last;
+  out->touched_total = d.touched_total;
+  out->updates = d.updates;
+  out->saturated = d.saturated;
+  out->occupied = occ;
+  for (int i = 0; i < 16; ++i) out->probe_hist[i] = d.probe_hist[i];
+  return PSF_OK;
+}
+
+PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
+                                    float* state_rgb, uint64_t cap, uint64_t* count,
+                                    psf_stream stream) {
+  if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  uint64_t occ = 0;
+  psf_status st = count_occupied(t, s, &occ);
+  if (st != PSF_OK) return st;
+  *count = occ;
+  if (occ > cap) return fail(PSF_BUFFER_TOO_SMALL, "more occupied cells than cap");
+  if (occ == 0) return PSF_OK;
+  // device scratch: cursor, keys, n_new, c_old, rgb
+  const size_t bytes = 256 + occ * 8 + occ * 4 * 2 + occ * 12;
+  char* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc export scratch");
+  auto* cur = reinterpret_cast<unsigned long long*>(d);
+  auto* dk = reinterpret_cast<unsigned long long*>(d + 256);
+  auto* dn = reinterpret_cast<uint32_t*>(d + 256 + occ * 8);
+  auto* dc = dn + occ;
+  auto* drgb = reinterpret_cast<float*>(dc + occ);
+  e = hipMemsetAsync(cur, 0, 8, s);
+  if (e == hipSuccess)
+    e = psf::launch_compact(t->tv, nslots(t), t->cfg.state_dtype, cur, occ, dk, dn, dc, drgb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(keys, dk, occ * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && n_new) e = hipMemcpyAsync(n_new, dn, occ * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && c_old) e = hipMemcpyAsync(c_old, dc, occ * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && state_rgb) {
+    for (int ch = 0; ch < 3 && e == hipSuccess; ++ch)
+      e = hipMemcpyAsync(state_rgb + ch * cap, drgb + ch * occ, occ * 4, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
+}
+
+PSF_API psf_status psf_iterate_batch(const psf_session* sessions, uint32_t k, psf_stream stream) {
+  if (k == 0) return PSF_OK;
+  if (!sessions) return fail(PSF_INVALID_ARGUMENT, "sessions is NULL");
+  for (uint32_t i = 0; i < k; ++i) {
+    const psf_session& ss = sessions[i];
+    psf_status st = psf_iterate(ss.table, &ss.rec, ss.n, &ss.q, ss.nq, ss.d_out_rgb, ss.d_out_found,
+                                stream);
+    if (st != PSF_OK) return st;
+  }
+  return PSF_OK;
+}
+
+PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* total_ms, int reset) {
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (!t->timer) return fail(PSF_NOT_SUPPORTED, "table was created without PSF_FLAG_TIMING");
+  hipError_t e = t->timer->flush();
+  if (e != hipSuccess) return hip_fail(e, "kernel timing");
+  for (int k = 0; k < PSF_K_COUNT; ++k) {
+    if (launches) launches[k] = t->timer->launches[k];
+    if (total_ms) total_ms[k] = t->timer->total_ms[k];
+    if (reset) {
+      t->timer->launches[k] = 0;
+      t->timer->total_ms[k] = 0.0;
+    }
+  }
+  return PSF_OK;
+}
+
+PSF_API const char* psf_kernel_name(uint32_t k) {
+  static const char* names[PSF_K_COUNT] = {"keys", "insert_direct", "bin", "merge", "merge_blend",
+                                           "update", "query", "batch"};
+  return k < PSF_K_COUNT ? names[k] : "";
+}
+
+PSF_API const char* psf_last_error(void) { return g_err.c_str(); }
+
+PSF_API const char* psf_version(void) { return "psf 0.1 gfx950"; }

@@ -1,0 +1,255 @@
+// Device-side definitions shared by the PSTF kernels: the cell key, the slot
+// hash, the table layout and the 16-bit state encodings.
+//
+// Everything here runs on gfx950 only.  The translation units that include
+// this header are compiled with -ffp-contract=off and correctly rounded FP32
+// division, so the floating point that decides a key is plain IEEE binary32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psf {
+
+constexpr uint64_t kEmpty = ~0ull;  // valid keys never set bit 63
+
+// Parameters of the key function (spatio-directional hashing, Sec. 2.6 of the
+// paper; the quantisation itself is this library's specification).
+struct KeyParams {
+  float cx, cy, cz;
+  float kappa;
+  int32_t e_min;
+  int32_t max_level;
+  int32_t nb_log2;
+  int32_t db_log2;
+  float rough_thr;
+};
+
+// One table slot, 32 bytes: everything a lookup needs sits in one sector.
+struct alignas(32) Slot {
+  unsigned long long key;  // kEmpty when free
+  uint32_t c_old;          // cumulative sample count (Sec. 2.4, c_h^old)
+  uint32_t pad;
+  uint32_t L[4];           // approximant: 3 x f32, or 3 x 16-bit packed in L[0..1]
+};
+
+// Per-slot accumulator of the current frame (Eq. 5-6 numerator / counter).
+struct alignas(16) Acc {
+  uint32_t n;
+  float s[3];
+};
+
+// Device-resident counters.
+struct alignas(256) DevStats {
+  unsigned long long skipped;
+  unsigned long long dropped;
+  unsigned long long coord_overflow;
+  unsigned long long touched_last;
+  unsigned long long touched_total;
+  unsigned long long updates;
+  unsigned long long saturated;
+  unsigned long long probe_hist[16];
+  uint32_t touched_count;  // cells blended by the running update
+  uint32_t done_blocks;    // completion counter of the update kernel
+  uint32_t query_skipped;
+  uint32_t pad;
+};
+
+// View of one table handed to kernels by value.
+struct TableView {
+  Slot* slots;
+  Acc* acc;
+  DevStats* stats;
+  uint32_t log2_slots;
+  uint32_t part_log2;   // slots per partition = 2^part_log2 (<= log2_slots)
+  uint32_t max_probe;
+  uint32_t flags;
+};
+
+struct BlendParams {
+  int32_t mode;     // 0 Eq. 11, 1 constant alpha, 2 linear
+  float alpha;
+  float inv_t_max;
+  int32_t dtype;    // 0 f32, 1 f16, 2 bf16
+};
+
+// ------------------------------------------------------------------ hashing
+// 64-bit finaliser of MurmurHash3 (A. Appleby, public domain).
+__device__ __forceinline__ uint64_t fmix64(uint64_t h) {
+  h ^= h >> 33;
+  h *= 0xff51afd7ed558ccdull;
+  h ^= h >> 33;
+  h *= 0xc4ceb9fe1a85ec53ull;
+  h ^= h >> 33;
+  return h;
+}
+
+// Probe sequence of a key: partition = top hash bits, start = low hash bits,
+// linear probing wraps inside the partition.
+struct ProbeSeq {
+  uint64_t base;
+  uint32_t start;
+  uint32_t mask;
+  __device__ __forceinline__ uint64_t at(uint32_t i) const { return base + ((start + i) & mask); }
+};
+
+__device__ __forceinline__ uint32_t partition_of(uint64_t h, uint32_t log2_slots, uint32_t part_log2) {
+  uint32_t pbits = log2_slots - part_log2;
+  return pbits == 0 ? 0u : (uint32_t)(h >> (64 - pbits));
+}
+
+__device__ __forceinline__ ProbeSeq probe_seq(uint64_t key, uint32_t log2_slots, uint32_t part_log2) {
+  uint64_t h = fmix64(key);
+  ProbeSeq p;
+  p.mask = (1u << part_log2) - 1u;
+  p.base = (uint64_t)partition_of(h, log2_slots, part_log2) << part_log2;
+  p.start = (uint32_t)h & p.mask;
+  return p;
+}
+
+// ------------------------------------------------------------------ key
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ bool finite3(float a, float b, float c) {
+  return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
+}
+
+// Level: floor(log2(kappa * d^2) / 2) clamped, read off the binary32 exponent.
+__device__ __forceinline__ int32_t cell_level(const KeyParams& kp, float px, float py, float pz) {
+  if (kp.kappa == 0.0f) return 0;
+  const float dx = px - kp.cx, dy = py - kp.cy, dz = pz - kp.cz;
+  const float d2 = (dx * dx + dy * dy) + dz * dz;
+  const float q = d2 * kp.kappa;
+  const int32_t biased = (int32_t)((__float_as_uint(q) >> 23) & 0xffu);
+  const int32_t e = biased ? biased - 127 : -127;
+  const int32_t lvl = e >> 1;  // arithmetic shift: floor(e / 2)
+  return lvl < 0 ? 0 : (lvl > kp.max_level ? kp.max_level : lvl);
+}
+
+// floor(p * 2^-shift) modulo 2^16, flagging values outside [-2^15, 2^15).
+__device__ __forceinline__ uint32_t grid16(float p, int32_t shift, bool& ovf) {
+  float f = floorf(ldexpf(p, -shift));
+  ovf |= !(f >= -32768.0f && f < 32768.0f);
+  f = fminf(fmaxf(f, -2147483648.0f), 2147483520.0f);
+  return (uint32_t)(int32_t)f & 0xffffu;
+}
+
+// Octahedral map of a direction onto a B x B grid (B = 2^b): index iu*B + iw.
+__device__ __forceinline__ uint32_t octa_bin(float x, float y, float z, int32_t b) {
+  const float B = (float)(1 << b);
+  const int32_t top = (1 << b) - 1;
+  const float l1 = (fabsf(x) + fabsf(y)) + fabsf(z);
+  float u = 0.0f, w = 0.0f;
+  if (l1 > 0.0f) {
+    u = x / l1;
+    w = y / l1;
+  }
+  if (z < 0.0f) {
+    const float fu = (1.0f - fabsf(w)) * (u >= 0.0f ? 1.0f : -1.0f);
+    const float fw = (1.0f - fabsf(u)) * (w >= 0.0f ? 1.0f : -1.0f);
+    u = fu;
+    w = fw;
+  }
+  int32_t iu = (int32_t)floorf((u * 0.5f + 0.5f) * B);
+  int32_t iw = (int32_t)floorf((w * 0.5f + 0.5f) * B);
+  iu = iu < 0 ? 0 : (iu > top ? top : iu);
+  iw = iw < 0 ? 0 : (iw > top ? top : iw);
+  return (uint32_t)(iu * (1 << b) + iw);
+}
+
+// Cell key of one vertex.  Returns false for rejected (non-finite) input.
+// has_rough is false when the caller supplied no roughness array (every
+// vertex diffuse); the direction is read only for glossy vertices.
+__device__ __forceinline__ bool cell_key(const KeyParams& kp, float px, float py, float pz, float nx,
+                                         float ny, float nz, float ox, float oy, float oz,
+                                         bool has_rough, float rough, uint64_t& key, bool& ovf) {
+  if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return false;
+  bool glossy = false;
+  if (has_rough) {
+    if (!__builtin_isfinite(rough)) return false;
+    glossy = rough < kp.rough_thr;
+    if (glossy && !finite3(ox, oy, oz)) return false;
+  }
+  const int32_t lvl = cell_level(kp, px, py, pz);
+  const int32_t shift = kp.e_min + lvl;
+  ovf = false;
+  const uint64_t ix = grid16(px, shift, ovf);
+  const uint64_t iy = grid16(py, shift, ovf);
+  const uint64_t iz = grid16(pz, shift, ovf);
+  const uint64_t nbin = octa_bin(nx, ny, nz, kp.nb_log2);
+  const uint64_t dbin = glossy ? octa_bin(ox, oy, oz, kp.db_log2) : 0ull;
+  key = ((uint64_t)lvl << 59) | ((uint64_t)glossy << 58) | (dbin << 52) | (nbin << 48) |
+        (iz << 32) | (iy << 16) | ix;
+  return true;
+}
+
+// ------------------------------------------------------------------ state encodings
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f, bool& sat) {
+  (void)sat;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ uint32_t f32_to_f16_rne(float f, bool& sat) {
+  if (fabsf(f) > 65504.0f) {
+    sat = true;
+    f = f > 0.0f ? 65504.0f : -65504.0f;
+  }
+  _Float16 h = (_Float16)f;  // v_cvt_f16_f32, round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+__device__ __forceinline__ void load_state(const Slot& s, int32_t dtype, float& r, float& g, float& b) {
+  if (dtype == 0) {
+    r = __uint_as_float(s.L[0]);
+    g = __uint_as_float(s.L[1]);
+    b = __uint_as_float(s.L[2]);
+  } else if (dtype == 1) {
+    r = f16_to_f32(s.L[0] & 0xffffu);
+    g = f16_to_f32(s.L[0] >> 16);
+    b = f16_to_f32(s.L[1] & 0xffffu);
+  } else {
+    r = bf16_to_f32(s.L[0] & 0xffffu);
+    g = bf16_to_f32(s.L[0] >> 16);
+    b = bf16_to_f32(s.L[1] & 0xffffu);
+  }
+}
+
+__device__ __forceinline__ void encode_state(int32_t dtype, float r, float g, float b, uint32_t out[4],
+                                             bool& sat) {
+  if (dtype == 0) {
+    out[0] = __float_as_uint(r);
+    out[1] = __float_as_uint(g);
+    out[2] = __float_as_uint(b);
+    out[3] = 0u;
+  } else if (dtype == 1) {
+    out[0] = f32_to_f16_rne(r, sat) | (f32_to_f16_rne(g, sat) << 16);
+    out[1] = f32_to_f16_rne(b, sat);
+    out[2] = 0u;
+    out[3] = 0u;
+  } else {
+    out[0] = f32_to_bf16_rne(r, sat) | (f32_to_bf16_rne(g, sat) << 16);
+    out[1] = f32_to_bf16_rne(b, sat);
+    out[2] = 0u;
+    out[3] = 0u;
+  }
+}
+
+// Eq. 10-11 for one cell, FP32.  n > 0.
+__device__ __forceinline__ float blend_alpha(const BlendParams& bp, uint32_t n, uint32_t c_old) {
+  const float nf = (float)n;
+  if (bp.mode == 1) return c_old == 0 ? 1.0f : bp.alpha;
+  const float ratio = nf / ((float)c_old + nf);
+  if (bp.mode == 2) return ratio;
+  return fmaxf(sqrtf(ratio), bp.inv_t_max);
+}
+
+}  // namespace psf

@@ -1,0 +1,53 @@
+// Host-visible declarations shared between the C-ABI layer and the kernel
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psf_device.h"
+
+namespace psf {
+
+struct RecPtrs {
+  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *r, *g, *b, *rough;
+};
+
+struct QryPtrs {
+  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *rough;
+};
+
+// Partitioned-insert working buffers of one table.
+struct PartView {
+  unsigned long long* stage_key;  // staged keys, grouped per tile by partition
+  float* stage_rgb;               // 3 x capacity, SoA
+  uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile
+  uint32_t tile;                  // records per binning tile (<= 65535)
+  uint32_t max_tiles;             // tiles per launch
+  uint64_t capacity;              // records per launch
+};
+
+hipError_t launch_keys(const RecPtrs& rec, uint64_t n, const KeyParams& kp, unsigned long long* out,
+                       hipStream_t s);
+hipError_t launch_insert_direct(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
+                                const TableView& tv, hipStream_t s);
+hipError_t launch_update(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s);
+hipError_t launch_query(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv,
+                        int32_t dtype, float* out, uint8_t* found, hipStream_t s);
+hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s);
+hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s);
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
+hipError_t launch_count_occupied(const TableView& tv, uint64_t nslots, unsigned long long* out,
+                                 hipStream_t s);
+// Partitioned insertion of n <= pv.capacity records: bin, then merge.
+// fuse != nullptr applies the temporal blend in the merge pass (the table
+// must hold no pending samples).
+hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
+                      const PartView& pv, hipStream_t s);
+hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
+                        hipStream_t s);
+hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
+                          unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
+                          uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);
+
+}  // namespace psf

@@ -1,0 +1,368 @@
+// PSTF hash-filter kernels for gfx950: direct (wave-merged) insertion, the
+// streaming temporal blend, lookups, key output, resets and
+// export support.  The partitioned insertion lives in psf_partition.hip.
+#include "psf_device.h"
+#include "psf_internal.h"
+
+namespace psf {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
+  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, (int)lane);
+  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Add a per-wave count to a device counter with one atomic from lane 0.
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m && lane_id() == (uint32_t)__ffsll((unsigned long long)m) - 1)
+    atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// Find or claim the slot of key along its probe sequence.  Returns the slot
+// index or ~0 when max_probe slots were all taken by other keys.  *probes
+// receives the number of slots examined.
+__device__ __forceinline__ uint64_t find_or_claim(const TableView& tv, uint64_t key, uint32_t* probes) {
+  const ProbeSeq ps = probe_seq(key, tv.log2_slots, tv.part_log2);
+  for (uint32_t i = 0; i < tv.max_probe; ++i) {
+    const uint64_t s = ps.at(i);
+    unsigned long long* kp = &tv.slots[s].key;
+    unsigned long long cur = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kEmpty) cur = atomicCAS(kp, kEmpty, (unsigned long long)key);
+    if (cur == kEmpty || cur == key) {
+      *probes = i + 1;
+      return s;
+    }
+  }
+  *probes = tv.max_probe;
+  return ~0ull;
+}
+
+__device__ __forceinline__ uint64_t find_slot(const TableView& tv, uint64_t key) {
+  const ProbeSeq ps = probe_seq(key, tv.log2_slots, tv.part_log2);
+  for (uint32_t i = 0; i < tv.max_probe; ++i) {
+    const uint64_t s = ps.at(i);
+    const unsigned long long cur = tv.slots[s].key;
+    if (cur == key) return s;
+    if (cur == kEmpty) return ~0ull;
+  }
+  return ~0ull;
+}
+
+// ------------------------------------------------------------------ keys
+__global__ void __launch_bounds__(256) k_keys(RecPtrs rec, uint64_t n, KeyParams kp,
+                                              unsigned long long* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t key;
+  bool ovf;
+  const bool hr = rec.rough != nullptr;
+  const bool g = hr && rec.rough[i] < kp.rough_thr;
+  const bool ok = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
+                           g ? rec.ox[i] : 0.0f, g ? rec.oy[i] : 0.0f, g ? rec.oz[i] : 0.0f, hr,
+                           hr ? rec.rough[i] : 0.0f, key, ovf);
+  out[i] = ok ? key : kEmpty;
+}
+
+// ------------------------------------------------------------------ direct insert
+// One record per lane.  Lanes of a wave holding the same key elect the lowest
+// lane as leader; sums are merged in LDS; each leader claims its slot with a
+// 64-bit CAS and adds the merged count and sums with global atomics.
+constexpr int kInsBlock = 256;
+
+__global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64_t n, KeyParams kp,
+                                                             TableView tv) {
+  __shared__ float s_sum[kInsBlock][3];
+  __shared__ uint32_t s_cnt[kInsBlock];
+  __shared__ uint32_t s_hist[16];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wbase = tid & ~63u;
+  const bool stats = (tv.flags & 1u) != 0;
+  if (stats && tid < 16) s_hist[tid] = 0;
+  s_sum[tid][0] = s_sum[tid][1] = s_sum[tid][2] = 0.0f;
+  s_cnt[tid] = 0;
+  __syncthreads();
+
+  const uint64_t i = (uint64_t)blockIdx.x * kInsBlock + tid;
+  bool valid = false;
+  bool skip = false;
+  uint64_t key = kEmpty;
+  bool ovf = false;
+  float r = 0.0f, g = 0.0f, b = 0.0f;
+  if (i < n) {
+    const bool hr = rec.rough != nullptr;
+    const float ro = hr ? rec.rough[i] : 0.0f;
+    const bool gl = hr && ro < kp.rough_thr;
+    r = rec.r[i];
+    g = rec.g[i];
+    b = rec.b[i];
+    valid = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
+                     gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro,
+                     key, ovf);
+    valid = valid && finite3(r, g, b);
+    skip = !valid;
+  }
+  wave_count(&tv.stats->skipped, skip);
+  wave_count(&tv.stats->coord_overflow, valid && ovf);
+
+  // elect a leader lane per distinct key
+  uint64_t pending = __ballot(valid);
+  uint32_t leader = 64;
+  while (pending) {
+    const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1;
+    const uint64_t lk = readlane64(key, l);
+    const bool mine = valid && leader == 64 && key == lk;
+    const uint64_t m = __ballot(mine);
+    if (mine) leader = l;
+    pending &= ~m;
+  }
+  if (valid) {
+    atomicAdd(&s_cnt[wbase + leader], 1u);
+    atomicAdd(&s_sum[wbase + leader][0], r);
+    atomicAdd(&s_sum[wbase + leader][1], g);
+    atomicAdd(&s_sum[wbase + leader][2], b);
+  }
+  __syncthreads();
+
+  const bool lead = valid && leader == lane;
+  uint64_t slot = ~0ull;
+  uint32_t cnt = 0;
+  if (lead) {
+    cnt = s_cnt[tid];
+    uint32_t probes;
+    slot = find_or_claim(tv, key, &probes);
+    if (slot != ~0ull) {
+      Acc* a = &tv.acc[slot];
+      atomicAdd(&a->n, cnt);
+      atomicAdd(&a->s[0], s_sum[tid][0]);
+      atomicAdd(&a->s[1], s_sum[tid][1]);
+      atomicAdd(&a->s[2], s_sum[tid][2]);
+      if (stats) atomicAdd(&s_hist[probes - 1 < 15 ? probes - 1 : 15], 1u);
+    } else {
+      atomicAdd(&tv.stats->dropped, (unsigned long long)cnt);
+    }
+  }
+  if (stats) {
+    __syncthreads();
+    if (tid < 16 && s_hist[tid]) atomicAdd(&tv.stats->probe_hist[tid], (unsigned long long)s_hist[tid]);
+  }
+}
+
+// ------------------------------------------------------------------ temporal update
+// Blend one slot's accumulated frame into its state (Eq. 10-11) and clear the
+// accumulator.  Returns true if the slot had samples.
+__device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParams& bp, uint64_t s,
+                                           bool& sat) {
+  const Acc a = tv.acc[s];
+  if (a.n == 0) return false;
+  Slot* d = &tv.slots[s];
+  const uint32_t c_old = d->c_old;
+  const float alpha = blend_alpha(bp, a.n, c_old);
+  const float inv = 1.0f / (float)a.n;
+  float L[3];
+  load_state(*d, bp.dtype, L[0], L[1], L[2]);
+  float out[3];
+  for (int c = 0; c < 3; ++c) {
+    const float m = a.s[c] * inv;
+    out[c] = alpha == 1.0f ? m : (1.0f - alpha) * L[c] + alpha * m;
+  }
+  uint32_t enc[4];
+  encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
+  d->c_old = c_old + a.n;
+  *reinterpret_cast<uint4*>(d->L) = make_uint4(enc[0], enc[1], enc[2], enc[3]);
+  tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
+  return true;
+}
+
+// Streaming pass over every slot's accumulator; the last block to finish
+// publishes the number of cells blended.
+__global__ void __launch_bounds__(256) k_update(TableView tv, BlendParams bp, uint64_t nslots) {
+  __shared__ uint32_t s_touched, s_sat;
+  if (threadIdx.x == 0) s_touched = s_sat = 0;
+  __syncthreads();
+  bool sat = false;
+  uint32_t touched = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    touched += blend_slot(tv, bp, s, sat) ? 1u : 0u;
+  for (int off = 32; off > 0; off >>= 1) touched += __shfl_xor(touched, off);
+  if (lane_id() == 0 && touched) atomicAdd(&s_touched, touched);
+  if (sat) atomicAdd(&s_sat, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_sat) atomicAdd(&tv.stats->saturated, (unsigned long long)s_sat);
+    if (s_touched) atomicAdd(&tv.stats->touched_count, s_touched);
+    __threadfence();
+    const uint32_t done = atomicAdd(&tv.stats->done_blocks, 1u);
+    if (done == gridDim.x - 1) {
+      const uint32_t cnt = __hip_atomic_load(&tv.stats->touched_count, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      tv.stats->touched_last = cnt;
+      tv.stats->touched_total += cnt;
+      tv.stats->updates += 1;
+      tv.stats->touched_count = 0;
+      tv.stats->done_blocks = 0;
+      __threadfence();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ query
+__global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams kp, TableView tv,
+                                               int32_t dtype, float* out, uint8_t* found) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t key;
+  bool ovf;
+  const bool hr = q.rough != nullptr;
+  const float ro = hr ? q.rough[i] : 0.0f;
+  const bool gl = hr && ro < kp.rough_thr;
+  float r = 0.0f, g = 0.0f, b = 0.0f;
+  uint8_t hit = 0;
+  if (cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
+               gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, key, ovf)) {
+    const uint64_t s = find_slot(tv, key);
+    if (s != ~0ull) {
+      const Slot sl = tv.slots[s];
+      if (sl.c_old > 0) {
+        load_state(sl, dtype, r, g, b);
+        hit = 1;
+      }
+    }
+  }
+  out[i] = r;
+  out[n + i] = g;
+  out[2 * n + i] = b;
+  if (found) found[i] = hit;
+}
+
+// ------------------------------------------------------------------ reset / init
+__global__ void k_clear(TableView tv, uint64_t nslots) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    Slot z;
+    z.key = kEmpty;
+    z.c_old = 0;
+    z.pad = 0;
+    z.L[0] = z.L[1] = z.L[2] = z.L[3] = 0;
+    tv.slots[s] = z;
+    tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tv.stats->touched_count = 0;
+    tv.stats->done_blocks = 0;
+  }
+}
+
+__global__ void k_reset_counters(TableView tv, uint64_t nslots) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    tv.slots[s].c_old = 0;
+}
+
+__global__ void k_zero_words(uint32_t* p, uint64_t words) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ export support
+__global__ void k_count_occupied(TableView tv, uint64_t nslots, unsigned long long* out) {
+  uint32_t c = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    c += tv.slots[s].key != kEmpty;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+__global__ void k_compact(TableView tv, uint64_t nslots, int32_t dtype, unsigned long long* cursor,
+                          uint64_t cap, unsigned long long* keys, uint32_t* n_new, uint32_t* c_old,
+                          float* rgb) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    const Slot sl = tv.slots[s];
+    if (sl.key == kEmpty) continue;
+    const unsigned long long at = atomicAdd(cursor, 1ull);
+    if (at >= cap) continue;
+    keys[at] = sl.key;
+    n_new[at] = tv.acc[s].n;
+    c_old[at] = sl.c_old;
+    float r, g, b;
+    load_state(sl, dtype, r, g, b);
+    rgb[at] = r;
+    rgb[cap + at] = g;
+    rgb[2 * cap + at] = b;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned grid_for(uint64_t n, unsigned block) {
+  uint64_t g = (n + block - 1) / block;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+static inline unsigned stride_grid(uint64_t n, unsigned block, unsigned cap) {
+  uint64_t g = (n + block - 1) / block;
+  if (g > cap) g = cap;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+hipError_t launch_keys(const RecPtrs& rec, uint64_t n, const KeyParams& kp, unsigned long long* out,
+                       hipStream_t s) {
+  k_keys<<<grid_for(n, 256), 256, 0, s>>>(rec, n, kp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_direct(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
+                                const TableView& tv, hipStream_t s) {
+  k_insert_direct<<<grid_for(n, kInsBlock), kInsBlock, 0, s>>>(rec, n, kp, tv);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s) {
+  k_update<<<stride_grid(nslots, 256, 2048), 256, 0, s>>>(tv, bp, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv,
+                        int32_t dtype, float* out, uint8_t* found, hipStream_t s) {
+  k_query<<<grid_for(n, 256), 256, 0, s>>>(q, n, kp, tv, dtype, out, found);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s) {
+  k_clear<<<stride_grid(nslots, 256, 8192), 256, 0, s>>>(tv, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s) {
+  k_reset_counters<<<stride_grid(nslots, 256, 8192), 256, 0, s>>>(tv, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s) {
+  const uint64_t words = bytes / 4;
+  k_zero_words<<<stride_grid(words, 256, 4096), 256, 0, s>>>(static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_occupied(const TableView& tv, uint64_t nslots, unsigned long long* out,
+                                 hipStream_t s) {
+  k_count_occupied<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
+                          unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
+                          uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s) {
+  k_compact<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, dtype, cursor, cap, keys,
+                                                          n_new, c_old, rgb);
+  return hipGetLastError();
+}
+
+}  // namespace psf

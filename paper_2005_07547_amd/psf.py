@@ -1,0 +1,308 @@
+"""ctypes binding of libpsf.so (include/psf.h).
+
+Argument marshalling only: every step of the hash path runs in the HIP
+kernels of the shared library.  The functions keep the C names; ``Table`` is
+a thin convenience wrapper that takes torch CUDA tensors (device memory) and
+the current torch stream.  There is no CPU fallback: if the library is
+missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsf.so")
+
+PSF_OK, PSF_INVALID_ARGUMENT, PSF_OUT_OF_MEMORY, PSF_BUFFER_TOO_SMALL, PSF_HIP_ERROR, \
+    PSF_NOT_SUPPORTED = range(6)
+PSF_ALPHA_PAPER, PSF_ALPHA_CONST, PSF_ALPHA_LINEAR = 0, 1, 2
+PSF_STATE_F32, PSF_STATE_F16, PSF_STATE_BF16 = 0, 1, 2
+PSF_RESET_COUNTERS, PSF_RESET_CLEAR, PSF_RESET_STATS = 1, 2, 4
+PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
+PSF_FLAG_PROBE_STATS = 1
+PSF_FLAG_TIMING = 2
+PSF_K_COUNT = 8
+
+REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
+QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough")
+
+
+class PsfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"psf status {status}: {msg}")
+        self.status = status
+
+
+class psf_config(ctypes.Structure):
+    _fields_ = [
+        ("log2_slots", ctypes.c_uint32), ("max_probe", ctypes.c_uint32),
+        ("cam", ctypes.c_float * 3), ("kappa", ctypes.c_float), ("e_min", ctypes.c_int32),
+        ("max_level", ctypes.c_int32), ("normal_bins_log2", ctypes.c_int32),
+        ("dir_bins_log2", ctypes.c_int32), ("rough_thr", ctypes.c_float),
+        ("alpha_mode", ctypes.c_int32), ("alpha", ctypes.c_float), ("t_max", ctypes.c_float),
+        ("state_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("insert_mode", ctypes.c_int32), ("part_log2", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint64),
+    ]
+
+
+class psf_records(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in REC_FIELDS]
+
+
+class psf_queries(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in QRY_FIELDS]
+
+
+class psf_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("skipped", ctypes.c_uint64), ("dropped", ctypes.c_uint64),
+        ("coord_overflow", ctypes.c_uint64), ("touched_last", ctypes.c_uint64),
+        ("touched_total", ctypes.c_uint64), ("updates", ctypes.c_uint64),
+        ("saturated", ctypes.c_uint64), ("occupied", ctypes.c_uint64),
+        ("probe_hist", ctypes.c_uint64 * 16),
+    ]
+
+
+class psf_session(ctypes.Structure):
+    _fields_ = [
+        ("table", ctypes.c_void_p), ("rec", psf_records), ("n", ctypes.c_uint64),
+        ("q", psf_queries), ("nq", ctypes.c_uint64), ("d_out_rgb", ctypes.c_void_p),
+        ("d_out_found", ctypes.c_void_p),
+    ]
+
+
+# (name, restype, argtypes) of every exported function, in header order
+_vp, _u64, _u32, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
+_P = ctypes.POINTER
+EXPORTS = [
+    ("psf_table_bytes", _sz, [_P(psf_config)]),
+    ("psf_create_table", ctypes.c_int, [_P(psf_config), _vp, _sz, _vp, _P(_vp)]),
+    ("psf_destroy", ctypes.c_int, [_vp]),
+    ("psf_insert_samples", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp]),
+    ("psf_temporal_update", ctypes.c_int, [_vp, _vp]),
+    ("psf_query", ctypes.c_int, [_vp, _P(psf_queries), _u64, _vp, _vp, _vp]),
+    ("psf_iterate", ctypes.c_int, [_vp, _P(psf_records), _u64, _P(psf_queries), _u64, _vp, _vp, _vp]),
+    ("psf_reset", ctypes.c_int, [_vp, _u32, _vp]),
+    ("psf_compute_keys", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp, _vp]),
+    ("psf_get_stats", ctypes.c_int, [_vp, _P(psf_stats), _vp]),
+    ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
+    ("psf_iterate_batch", ctypes.c_int, [_P(psf_session), _u32, _vp]),
+    ("psf_kernel_times", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    ("psf_kernel_name", ctypes.c_char_p, [_u32]),
+    ("psf_last_error", ctypes.c_char_p, []),
+    ("psf_version", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpsf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2005_07547_amd/build.py "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in EXPORTS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != PSF_OK:
+        raise PsfError(status, load().psf_last_error().decode())
+
+
+def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0,
+                max_level=15, normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
+                alpha_mode=PSF_ALPHA_PAPER, alpha=0.2, t_max=5.0, state_dtype=PSF_STATE_F32,
+                flags=0, insert_mode=PSF_INSERT_AUTO, part_log2=0, max_batch=0, **_ignored):
+    c = psf_config()
+    c.log2_slots, c.max_probe = int(log2_slots), int(max_probe)
+    c.cam[:] = [float(x) for x in cam]
+    c.kappa, c.e_min, c.max_level = float(kappa), int(e_min), int(max_level)
+    c.normal_bins_log2, c.dir_bins_log2 = int(normal_bins_log2), int(dir_bins_log2)
+    c.rough_thr, c.alpha_mode, c.alpha, c.t_max = float(rough_thr), int(alpha_mode), float(alpha), float(t_max)
+    c.state_dtype, c.flags, c.insert_mode = int(state_dtype), int(flags), int(insert_mode)
+    c.part_log2, c.max_batch = int(part_log2), int(max_batch)
+    return c
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _device_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"field {name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+def make_records(rec: dict):
+    s = psf_records()
+    for f in REC_FIELDS:
+        v = rec.get(f)
+        setattr(s, f, None if v is None else _ptr(_device_f32(v, f)))
+    return s
+
+
+def make_queries(q: dict):
+    s = psf_queries()
+    for f in QRY_FIELDS:
+        v = q.get(f)
+        setattr(s, f, None if v is None else _ptr(_device_f32(v, f)))
+    return s
+
+
+def current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Table:
+    """One hash table in device memory (owned by a torch tensor)."""
+
+    def __init__(self, **cfg):
+        import torch
+        self._lib = load()
+        self.cfg = make_config(**cfg)
+        nbytes = self._lib.psf_table_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise PsfError(PSF_INVALID_ARGUMENT, self._lib.psf_last_error().decode())
+        self.nbytes = int(nbytes)
+        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.buffer.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        _check(self._lib.psf_create_table(ctypes.byref(self.cfg), ctypes.c_void_p(aligned),
+                                          self.nbytes, current_stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self._lib.psf_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_slots(self):
+        return 1 << self.cfg.log2_slots
+
+    def insert(self, rec: dict, n: int | None = None):
+        n = int(rec["px"].numel()) if n is None else int(n)
+        r = make_records(rec)
+        _check(self._lib.psf_insert_samples(self.handle, ctypes.byref(r), n, current_stream()))
+
+    def update(self):
+        _check(self._lib.psf_temporal_update(self.handle, current_stream()))
+
+    def query(self, q: dict, n: int | None = None, out=None, found=None):
+        import torch
+        n = int(q["px"].numel()) if n is None else int(n)
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device="cuda")
+        qs = make_queries(q)
+        _check(self._lib.psf_query(self.handle, ctypes.byref(qs), n, ctypes.c_void_p(_ptr(out)),
+                                   ctypes.c_void_p(_ptr(found)), current_stream()))
+        return out, found
+
+    def iterate(self, rec: dict, q: dict | None = None, out=None, found=None):
+        import torch
+        n = int(rec["px"].numel())
+        q = rec if q is None else q
+        nq = int(q["px"].numel())
+        if out is None:
+            out = torch.empty((3, nq), dtype=torch.float32, device="cuda")
+        if found is None:
+            found = torch.empty(nq, dtype=torch.uint8, device="cuda")
+        r = make_records(rec)
+        qs = make_queries(q)
+        _check(self._lib.psf_iterate(self.handle, ctypes.byref(r), n, ctypes.byref(qs), nq,
+                                     ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_ptr(found)),
+                                     current_stream()))
+        return out, found
+
+    def keys(self, rec: dict):
+        import torch
+        n = int(rec["px"].numel())
+        out = torch.empty(n, dtype=torch.int64, device="cuda")
+        r = make_records({k: v for k, v in rec.items() if k in REC_FIELDS})
+        _check(self._lib.psf_compute_keys(self.handle, ctypes.byref(r), n,
+                                          ctypes.c_void_p(_ptr(out)), current_stream()))
+        return out
+
+    def reset(self, what: int):
+        _check(self._lib.psf_reset(self.handle, int(what), current_stream()))
+
+    def stats(self) -> dict:
+        s = psf_stats()
+        _check(self._lib.psf_get_stats(self.handle, ctypes.byref(s), current_stream()))
+        d = {f: getattr(s, f) for f, _ in psf_stats._fields_ if f != "probe_hist"}
+        d["probe_hist"] = list(s.probe_hist)
+        return d
+
+    def kernel_times(self, reset=False) -> dict:
+        """{kernel name: (launches, total ms)} for tables made with PSF_FLAG_TIMING."""
+        import numpy as np
+        launches = np.zeros(PSF_K_COUNT, dtype=np.uint64)
+        ms = np.zeros(PSF_K_COUNT, dtype=np.float64)
+        _check(self._lib.psf_kernel_times(self.handle, launches.ctypes.data, ms.ctypes.data,
+                                          1 if reset else 0))
+        return {self._lib.psf_kernel_name(k).decode(): (int(launches[k]), float(ms[k]))
+                for k in range(PSF_K_COUNT) if launches[k]}
+
+    def export(self):
+        """Occupied cells as numpy arrays: keys (uint64), n_new, c_old, L (3 x C)."""
+        import numpy as np
+        st = self.stats()
+        cap = max(1, int(st["occupied"]))
+        keys = np.zeros(cap, dtype=np.uint64)
+        n_new = np.zeros(cap, dtype=np.uint32)
+        c_old = np.zeros(cap, dtype=np.uint32)
+        rgb = np.zeros((3, cap), dtype=np.float32)
+        count = ctypes.c_uint64()
+        _check(self._lib.psf_export_cells(self.handle, keys.ctypes.data, n_new.ctypes.data,
+                                          c_old.ctypes.data, rgb.ctypes.data, cap,
+                                          ctypes.byref(count), current_stream()))
+        c = int(count.value)
+        order = np.argsort(keys[:c], kind="stable")
+        return {"keys": keys[:c][order], "n_new": n_new[:c][order], "c_old": c_old[:c][order],
+                "L": rgb[:, :c][:, order]}
+
+
+def iterate_batch(tables, recs, queries, outs, founds):
+    """One batched iteration over several tables (psf_iterate_batch)."""
+    lib = load()
+    k = len(tables)
+    arr = (psf_session * k)()
+    for i in range(k):
+        s = arr[i]
+        s.table = tables[i].handle
+        s.rec = make_records(recs[i])
+        s.n = int(recs[i]["px"].numel())
+        s.q = make_queries(queries[i])
+        s.nq = int(queries[i]["px"].numel())
+        s.d_out_rgb = _ptr(outs[i])
+        s.d_out_found = _ptr(founds[i]) if founds[i] is not None else None
+    _check(lib.psf_iterate_batch(arr, k, current_stream()))
+
+
+def version() -> str:
+    return load().psf_version().decode()

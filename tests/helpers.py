@@ -46,3 +46,36 @@ def concat(recs):
 
 def take(rec, idx):
     return {k: (None if v is None else np.ascontiguousarray(v[idx])) for k, v in rec.items()}
+
+
+# ----------------------------------------------------------------- GPU side
+def to_device(rec):
+    import torch
+    return {k: (None if v is None else torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).cuda())
+            for k, v in rec.items()}
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def rel_err(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    den = np.maximum(np.abs(want), 1e-30)
+    return np.abs(got - want) / den
+
+
+def compare_cells(gpu_ex, orc_ex, rtol, label=""):
+    """Keys and counts bit-exact, approximant within rtol (relative)."""
+    assert np.array_equal(gpu_ex["keys"], orc_ex["keys"]), f"{label}: key sets differ"
+    assert np.array_equal(gpu_ex["c_old"].astype(np.uint64), orc_ex["c_old"]), f"{label}: c_old differs"
+    assert np.array_equal(gpu_ex["n_new"].astype(np.uint64), orc_ex["n_new"]), f"{label}: n_new differs"
+    e = rel_err(gpu_ex["L"], orc_ex["L"])
+    worst = float(e.max()) if e.size else 0.0
+    assert worst <= rtol, f"{label}: worst relative error {worst:.3e} > {rtol:.1e}"
+    return worst

@@ -1,0 +1,378 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Keys, cell sets and counts must match bit for bit; the FP32 approximant must
+be within 1e-5 relative of the binary64 oracle.  Covers both insert
+strategies, the fused iteration, every temporal mode, ragged and empty
+inputs, non-finite records, table overflow, resets, and the full-size plain
+workload (sampled cells).
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import (compare_cells, concat, golden_rows, records, rel_err, take, to_device)
+
+pytestmark = pytest.mark.gpu
+
+RTOL_F32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def psf(torch_cuda):
+    from paper_2005_07547_amd import psf as P
+    P.load()
+    return P
+
+
+def _oracle(cfg):
+    import oracle
+    return oracle.Oracle(**cfg)
+
+
+def _table(psf, cfg, **extra):
+    c = dict(cfg)
+    c.update(extra)
+    return psf.Table(**c)
+
+
+def _tiny(it, alpha_mode=1):
+    from synth import workloads as W
+    wl = W.tiny(alpha_mode=alpha_mode)
+    rec = dict(W.make_scene(wl).generate(wl["gen"], it))
+    rec["rough"] = None
+    return wl, rec
+
+
+def _gpu_export(t):
+    return t.export()
+
+
+# ----------------------------------------------------------------- keys
+def test_keys_golden_vectors(psf, torch_cuda):
+    for row in golden_rows("key_vectors.txt"):
+        kappa, e_min, max_level, thr = row[0].split()
+        p = [np.float32(float(x)) for x in row[1].split()]
+        nrm = [np.float32(float(x)) for x in row[2].split()]
+        o = [np.float32(float(x)) for x in row[3].split()]
+        rough = None if row[4] == "-" else [np.float32(float(row[4]))]
+        t = psf.Table(log2_slots=8, kappa=float(kappa), e_min=int(e_min), max_level=int(max_level),
+                      rough_thr=float(thr))
+        rec = records(1, px=[p[0]], py=[p[1]], pz=[p[2]], nx=[nrm[0]], ny=[nrm[1]], nz=[nrm[2]],
+                      ox=[o[0]], oy=[o[1]], oz=[o[2]], rough=rough)
+        k = int(t.keys(to_device(rec)).cpu().numpy().view(np.uint64)[0])
+        want = 0xFFFFFFFFFFFFFFFF if row[5] == "SKIP" else int(row[5], 16)
+        assert k == want, (row, hex(k))
+
+
+def _adversarial(n, seed):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-40, 40, size=(3, n)).astype(np.float32)
+    # snap a third of the coordinates onto cell boundaries of several levels
+    snap = rng.random((3, n)) < 0.33
+    grid = 2.0 ** rng.integers(-7, 3, size=(3, n))
+    p = np.where(snap, (np.round(p / grid) * grid).astype(np.float32), p)
+    p[:, ::97] = -0.0
+    p[0, 5::101] = np.float32(1e-40)   # subnormal
+    p[1, 7::103] = np.float32(-1e-40)
+    p[2, 9::89] = np.float32(3e38)
+    v = rng.normal(size=(3, n))
+    v[:, ::7] = np.round(v[:, ::7])    # axis-aligned and diagonal directions
+    v = (v / np.maximum(np.abs(v).sum(axis=0), 1e-30)).astype(np.float32)
+    v[:, ::211] = 0.0
+    w = rng.normal(size=(3, n)).astype(np.float32)
+    w[:, ::13] = np.round(w[:, ::13])
+    rough = rng.uniform(0.0, 0.6, size=n).astype(np.float32)
+    rough[::17] = np.float32(0.3)
+    bad = rng.choice(n, size=n // 50, replace=False)
+    p[0, bad[: len(bad) // 3]] = np.nan
+    v[1, bad[len(bad) // 3: 2 * len(bad) // 3]] = np.inf
+    rough[bad[2 * len(bad) // 3:]] = np.nan
+    return records(n, px=p[0], py=p[1], pz=p[2], nx=v[0], ny=v[1], nz=v[2], ox=w[0], oy=w[1],
+                   oz=w[2], rough=rough)
+
+
+@pytest.mark.parametrize("kappa,e_min,max_level", [(0.0, 0, 15), (0.37, -3, 9), (2.5e-3, -6, 15),
+                                                    (1e30, 2, 4)])
+def test_keys_bit_exact_adversarial(psf, kappa, e_min, max_level):
+    cfg = dict(cam=(0.3, -1.0, 2.0), kappa=kappa, e_min=e_min, max_level=max_level,
+               normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3)
+    rec = _adversarial(200003, seed=int(kappa * 7) + e_min + 100)
+    want, _ = _oracle(cfg).keys(rec)
+    got = _table(psf, cfg, log2_slots=8).keys(to_device(rec)).cpu().numpy().view(np.uint64)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} key mismatches, first at {bad[:5]}"
+
+
+def test_keys_bit_exact_workloads(psf):
+    from synth import workloads as W
+    for wl in (W.tiny(), W.plain()):
+        rec = W.make_scene(wl).generate(wl["gen"], 5)
+        if wl["diffuse_only"]:
+            rec = dict(rec)
+            rec["rough"] = None
+        want, _ = _oracle(wl["table"]).keys(rec)
+        got = _table(psf, wl["table"]).keys(to_device(rec)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, want), wl["name"]
+
+
+# ----------------------------------------------------------------- whole iterations
+MODES = [("direct", 1, False), ("partitioned", 2, False), ("fused", 2, True), ("fused-auto", 0, True)]
+
+
+@pytest.mark.parametrize("alpha_mode", [0, 1, 2])
+@pytest.mark.parametrize("name,insert_mode,fused", MODES)
+def test_tiny_workload_all_iterations(psf, torch_cuda, name, insert_mode, fused, alpha_mode):
+    wl, _ = _tiny(0, alpha_mode)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    for it in range(wl["iterations"]):
+        _, rec = _tiny(it, alpha_mode)
+        d = to_device(rec)
+        orc.insert(rec)
+        orc.update()
+        if fused:
+            out, found = t.iterate(d)
+        else:
+            t.insert(d)
+            t.update()
+            out, found = t.query(d)
+        torch_cuda.cuda.synchronize()
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found), (name, it)
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, (name, it)
+    compare_cells(t.export(), orc.export(), RTOL_F32, name)
+    st = t.stats()
+    assert st["dropped"] == 0 and st["skipped"] == 0
+    assert st["updates"] == wl["iterations"]
+
+
+@pytest.mark.parametrize("name,insert_mode,fused", MODES[:3])
+def test_plain_workload_full_parity_first_iterations(psf, torch_cuda, name, insert_mode, fused):
+    from synth import workloads as W
+    wl = W.plain()
+    sc = W.make_scene(wl)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    for it in range(2):
+        rec = sc.generate(wl["gen"], it)
+        d = to_device(rec)
+        orc.insert(rec)
+        orc.update()
+        if fused:
+            out, found = t.iterate(d)
+        else:
+            t.insert(d)
+            t.update()
+            out, found = t.query(d)
+        torch_cuda.cuda.synchronize()
+    worst = compare_cells(t.export(), orc.export(), RTOL_F32, name)
+    w_out, w_found = orc.query(rec)
+    assert np.array_equal(found.cpu().numpy(), w_found)
+    assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+    print(f"{name}: worst cell relative error {worst:.2e}")
+
+
+def test_plain_workload_sampled_cells_many_iterations(psf, torch_cuda):
+    """Full-size plain workload in the launch configuration the benchmark
+    times (fused partitioned iteration, 2^22 slots); the oracle tracks a
+    sample of cells over every iteration."""
+    from synth import workloads as W
+    wl = W.plain()
+    iters = 8
+    sc = W.make_scene(wl)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"])
+    first = sc.generate(wl["gen"], 0)
+    keys0, _ = orc.keys(first)
+    rng = np.random.default_rng(1)
+    sample = np.unique(rng.choice(keys0[keys0 != np.uint64(2**64 - 1)], size=3000))
+    orc.set_filter(sample)
+    submitted = 0
+    for it in range(iters):
+        rec = first if it == 0 else sc.generate(wl["gen"], it)
+        orc.insert(rec)
+        orc.update()
+        t.iterate(to_device(rec))
+        submitted += len(rec["px"])
+    torch_cuda.cuda.synchronize()
+    g = t.export()
+    o = orc.export()
+    idx = np.searchsorted(g["keys"], o["keys"])
+    assert np.all(g["keys"][idx] == o["keys"])
+    sub = {k: (v[:, idx] if v.ndim == 2 else v[idx]) for k, v in g.items()}
+    compare_cells(sub, o, RTOL_F32, "sampled")
+    st = t.stats()
+    assert st["dropped"] == 0 and st["skipped"] == 0
+    assert st["submitted"] == submitted
+    assert st["occupied"] <= t.n_slots * 0.6
+
+
+# ----------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("insert_mode", [1, 2])
+@pytest.mark.parametrize("n", [1, 63, 65, 1023, 8191, 8193, 100003])
+def test_ragged_sizes(psf, torch_cuda, insert_mode, n):
+    wl, rec = _tiny(3, 0)
+    rec = take(rec, np.arange(n) % len(rec["px"]))
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    orc.insert(rec)
+    orc.update()
+    t.insert(to_device(rec))
+    t.update()
+    compare_cells(t.export(), orc.export(), RTOL_F32, f"n={n}")
+
+
+def test_empty_inputs_are_noops(psf, torch_cuda):
+    wl, rec = _tiny(0, 0)
+    t = _table(psf, wl["table"])
+    d = to_device(rec)
+    t.insert(d, n=0)
+    out, found = t.query(d, n=0)
+    t.update()
+    st = t.stats()
+    assert st["occupied"] == 0 and st["touched_last"] == 0
+
+
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_nonfinite_records_are_skipped(psf, torch_cuda, insert_mode):
+    wl, rec = _tiny(1, 0)
+    n = len(rec["px"])
+    rec["px"][::101] = np.nan
+    rec["nz"][5::103] = np.inf
+    rec["g"][7::107] = -np.inf
+    orc = _oracle(wl["table"])
+    orc.insert(rec)
+    orc.update()
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    t.insert(to_device(rec))
+    t.update()
+    compare_cells(t.export(), orc.export(), RTOL_F32)
+    assert t.stats()["skipped"] == orc.counters()["skipped"] > 0
+    out, found = t.query(to_device(rec))
+    w_out, w_found = orc.query(rec)
+    assert np.array_equal(found.cpu().numpy(), w_found)
+
+
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_overflowing_table_conserves_counts(psf, torch_cuda, insert_mode):
+    # 2^4 slots and many more cells: every record is either in a cell or
+    # counted as dropped, and the cells that made it match the oracle
+    wl, rec = _tiny(2, 0)
+    cfg = dict(wl["table"], log2_slots=4, max_probe=16)
+    t = _table(psf, cfg, insert_mode=insert_mode)
+    t.insert(to_device(rec))
+    ex = t.export()
+    st = t.stats()
+    n = len(rec["px"])
+    assert len(ex["keys"]) == 16
+    assert st["dropped"] > 0
+    assert int(ex["n_new"].sum()) + st["dropped"] + st["skipped"] == n
+    orc = _oracle(wl["table"])
+    orc.insert(rec)
+    o = orc.export()
+    idx = np.searchsorted(o["keys"], ex["keys"])
+    assert np.array_equal(o["keys"][idx], ex["keys"])
+    assert np.array_equal(o["n_new"][idx], ex["n_new"].astype(np.uint64))
+
+
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_max_probe_one(psf, torch_cuda, insert_mode):
+    wl, rec = _tiny(4, 0)
+    cfg = dict(wl["table"], log2_slots=12, max_probe=1)
+    t = _table(psf, cfg, insert_mode=insert_mode)
+    t.insert(to_device(rec))
+    st = t.stats()
+    ex = t.export()
+    assert int(ex["n_new"].sum()) + st["dropped"] == len(rec["px"])
+    assert st["dropped"] > 0
+
+
+def test_coordinate_overflow_counted(psf, torch_cuda):
+    cfg = dict(kappa=0.0, e_min=-10, log2_slots=10)
+    rec = records(4, px=[0.0, 40.0, -40.0, 31.9], r=[1, 2, 3, 4])
+    orc = _oracle(cfg)
+    orc.insert(rec)
+    t = _table(psf, cfg)
+    t.insert(to_device(rec))
+    assert t.stats()["coord_overflow"] == orc.counters()["coord_overflow"] == 2
+
+
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_reset_semantics(psf, torch_cuda, insert_mode):
+    wl, rec = _tiny(5, 0)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    d = to_device(rec)
+    out, found = t.query(d)
+    assert int(found.sum()) == 0  # nothing blended yet
+    for what in (psf.PSF_RESET_COUNTERS, psf.PSF_RESET_CLEAR):
+        for _ in range(2):
+            orc.insert(rec)
+            orc.update()
+            t.insert(d)
+            t.update()
+        orc.reset(what)
+        t.reset(what)
+        out, found = t.query(d)
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found)
+        orc.insert(rec)
+        orc.update()
+        t.insert(d)
+        t.update()
+        compare_cells(t.export(), orc.export(), RTOL_F32, f"reset {what}")
+
+
+def test_multiple_inserts_before_update(psf, torch_cuda):
+    wl, rec = _tiny(6, 0)
+    for mode in (1, 2):
+        orc = _oracle(wl["table"])
+        orc.insert(rec)
+        orc.update()
+        t = _table(psf, wl["table"], insert_mode=mode)
+        parts = np.array_split(np.arange(len(rec["px"])), 3)
+        for p in parts:
+            t.insert(to_device(take(rec, p)))
+        t.update()
+        compare_cells(t.export(), orc.export(), RTOL_F32, f"mode {mode}")
+
+
+def test_insert_larger_than_batch_capacity(psf, torch_cuda):
+    wl, rec = _tiny(7, 0)
+    big = concat([rec] * 5)
+    orc = _oracle(wl["table"])
+    orc.insert(big)
+    orc.update()
+    t = _table(psf, wl["table"], insert_mode=2, max_batch=10000)
+    out, found = t.iterate(to_device(big))
+    compare_cells(t.export(), orc.export(), RTOL_F32)
+
+
+def test_invalid_arguments(psf, torch_cuda):
+    import ctypes
+    lib = psf.load()
+    bad = psf.make_config(log2_slots=3)
+    h = ctypes.c_void_p()
+    assert lib.psf_create_table(ctypes.byref(bad), None, 0, None, ctypes.byref(h)) == psf.PSF_INVALID_ARGUMENT
+    assert b"log2_slots" in lib.psf_last_error()
+    good = psf.make_config(log2_slots=10)
+    need = lib.psf_table_bytes(ctypes.byref(good))
+    buf = torch_cuda.empty(need, dtype=torch_cuda.uint8, device="cuda")
+    assert lib.psf_create_table(ctypes.byref(good), ctypes.c_void_p(buf.data_ptr()), need - 1, None,
+                                ctypes.byref(h)) == psf.PSF_BUFFER_TOO_SMALL
+    t = psf.Table(log2_slots=10)
+    empty = psf.psf_records()
+    assert lib.psf_insert_samples(t.handle, ctypes.byref(empty), 10, None) == psf.PSF_INVALID_ARGUMENT
+    assert lib.psf_insert_samples(t.handle, None, 10, None) == psf.PSF_INVALID_ARGUMENT
+    assert lib.psf_insert_samples(t.handle, None, 0, None) == psf.PSF_OK
+    assert lib.psf_reset(t.handle, 64, None) == psf.PSF_INVALID_ARGUMENT
+    for kw in (dict(alpha_mode=1, alpha=0.0), dict(t_max=0.5), dict(kappa=-1.0), dict(max_level=16),
+               dict(dir_bins_log2=4), dict(state_dtype=3), dict(part_log2=5), dict(max_probe=0)):
+        c = psf.make_config(log2_slots=10, **kw)
+        assert lib.psf_table_bytes(ctypes.byref(c)) == 0, kw
