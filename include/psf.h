@@ -134,6 +134,10 @@ typedef struct psf_config {
                                 (0 = default 11, else 8..12) */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M); larger inserts are split */
+  uint32_t bin_per;          /* partitioned insert: records per thread of the
+                                binning pass (0 = default 16, else 8, 12, 16);
+                                a binning tile is 512 * bin_per records */
+  uint32_t reserved;         /* must be 0 */
 } psf_config;
 
 /* Vertex records, structure of arrays, N float32 each (device memory).

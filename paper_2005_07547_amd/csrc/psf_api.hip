@@ -67,6 +67,8 @@ struct psf_table {
   psf::PartView pv{};
   bool partitioned = false;  // strategy used by inserts
   uint64_t submitted = 0;
+  uint64_t updates = 0;
+  uint32_t touch_entries = 0;  // BlockTouch entries written by the last blend
   bool pending = false;      // accumulators hold samples not yet blended
   hipStream_t last = nullptr;
 };
@@ -109,8 +111,8 @@ hipError_t timed(psf_table* t, int kind, hipStream_t s, F&& launch) {
 }
 
 constexpr uint32_t kDefaultPartLog2 = 11;
+constexpr uint32_t kDefaultBinPer = 16;
 constexpr uint64_t kDefaultBatch = 1ull << 22;
-constexpr uint32_t kTile = 8192;          // records per binning tile
 constexpr uint32_t kMaxPartitions = 1u << 13;  // LDS histogram of the binning pass
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -142,11 +144,14 @@ bool validate(const psf_config* c, std::string* why) {
   if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
   if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING)) return bad("unknown flags");
   if (c->max_batch > (1ull << 32)) return bad("max_batch must be <= 2^32");
+  if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
+  if (c->reserved != 0) return bad("reserved must be 0");
   return true;
 }
 
 struct Layout {
-  size_t stats = 0, slots = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0, total = 0;
+  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0,
+         rkeys = 0, total = 0;
   uint32_t part_log2 = 0;
   bool part = false;
   uint64_t cap = 0;
@@ -163,20 +168,27 @@ Layout layout_of(const psf_config& c) {
   size_t off = 0;
   L.stats = off;
   off = align_up(off + sizeof(psf::DevStats), 256);
+  L.touch = off;
+  off = align_up(off + psf::kTouchEntries * sizeof(psf::BlockTouch), 256);
   L.slots = off;
   off = align_up(off + S * sizeof(psf::Slot), 256);
+  L.keys = off;
+  off = align_up(off + S * 8, 256);
   L.acc = off;
   off = align_up(off + S * sizeof(psf::Acc), 256);
   if (L.part) {
+    const uint64_t tile = psf::bin_tile(c.bin_per ? c.bin_per : kDefaultBinPer);
     L.cap = c.max_batch ? c.max_batch : kDefaultBatch;
-    L.tiles = (uint32_t)((L.cap + kTile - 1) / kTile);
-    L.cap = (uint64_t)L.tiles * kTile;
+    L.tiles = (uint32_t)((L.cap + tile - 1) / tile);
+    L.cap = (uint64_t)L.tiles * tile;
     L.stage_key = off;
     off = align_up(off + L.cap * 8, 256);
     L.stage_rgb = off;
     off = align_up(off + L.cap * 12, 256);
     L.runs = off;
     off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
+    L.rkeys = off;
+    off = align_up(off + L.cap * 8, 256);
   }
   L.total = off;
   return L;
@@ -250,7 +262,15 @@ psf_status do_update(psf_table* t, hipStream_t s) {
   hipError_t e = timed(t, PSF_K_UPDATE, s, [&] { return psf::launch_update(t->tv, t->bp, nslots(t), s); });
   if (e != hipSuccess) return hip_fail(e, "update launch");
   t->pending = false;
+  t->updates++;
+  t->touch_entries = psf::update_grid(nslots(t));
   return PSF_OK;
+}
+
+bool same_vertices(const psf_records* r, const psf_queries* q) {
+  return r->px == q->px && r->py == q->py && r->pz == q->pz && r->nx == q->nx && r->ny == q->ny &&
+         r->nz == q->nz && r->rough == q->rough &&
+         (!r->rough || (r->ox == q->ox && r->oy == q->oy && r->oz == q->oz));
 }
 
 psf_status do_query(psf_table* t, const psf::QryPtrs& q, uint64_t n, float* out, uint8_t* found,
@@ -302,7 +322,9 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   }
   char* b = static_cast<char*>(t->base);
   t->tv.stats = reinterpret_cast<psf::DevStats*>(b + L.stats);
+  t->tv.touch = reinterpret_cast<psf::BlockTouch*>(b + L.touch);
   t->tv.slots = reinterpret_cast<psf::Slot*>(b + L.slots);
+  t->tv.keys = reinterpret_cast<unsigned long long*>(b + L.keys);
   t->tv.acc = reinterpret_cast<psf::Acc*>(b + L.acc);
   t->tv.log2_slots = cfg->log2_slots;
   t->tv.part_log2 = L.part_log2;
@@ -316,7 +338,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
     t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
     t->pv.stage_rgb = reinterpret_cast<float*>(b + L.stage_rgb);
     t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
-    t->pv.tile = kTile;
+    t->pv.rkeys = reinterpret_cast<unsigned long long*>(b + L.rkeys);
+    t->pv.tile = psf::bin_tile(cfg->bin_per ? cfg->bin_per : kDefaultBinPer);
     t->pv.max_tiles = L.tiles;
     t->pv.capacity = L.cap;
     t->partitioned = true;
@@ -327,7 +350,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
     t->timer = new (std::nothrow) KernelTimer();
     e = t->timer ? t->timer->init() : hipErrorOutOfMemory;
   }
-  if (e == hipSuccess) e = psf::launch_zero(t->tv.stats, sizeof(psf::DevStats), s);
+  if (e == hipSuccess) e = psf::launch_zero(t->tv.stats, L.slots - L.stats, s);
   if (e == hipSuccess) e = psf::launch_clear(t->tv, nslots(t), s);
   if (e != hipSuccess) {
     if (t->timer) {
@@ -405,6 +428,16 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
       e = timed(t, PSF_K_MERGE_BLEND, s, [&] { return psf::launch_merge(n, t->tv, t->pv, &t->bp, s); });
     if (e != hipSuccess) return hip_fail(e, "fused insert launch");
     t->submitted += n;
+    t->updates++;
+    t->touch_entries = 1u << (t->cfg.log2_slots - t->tv.part_log2);
+    if (nq == n && same_vertices(rec, q)) {
+      // the queries are the records just binned: reuse their keys
+      e = timed(t, PSF_K_QUERY, s, [&] {
+        return psf::launch_query_cached(t->pv.rkeys, n, t->tv, t->cfg.state_dtype, d_out_rgb,
+                                        d_out_found, s);
+      });
+      return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
+    }
   } else {
     if (n > 0) st = do_insert(t, rec_ptrs(rec), n, s);
     if (st == PSF_OK) st = do_update(t, s);
@@ -427,8 +460,10 @@ PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
     e = psf::launch_reset_counters(t->tv, nslots(t), s);
   }
   if (e == hipSuccess && (what & PSF_RESET_STATS)) {
-    e = psf::launch_zero(t->tv.stats, sizeof(psf::DevStats), s);
+    e = psf::launch_zero(t->tv.stats, reinterpret_cast<char*>(t->tv.slots) - reinterpret_cast<char*>(t->tv.stats), s);
     t->submitted = 0;
+    t->updates = 0;
+    t->touch_entries = 0;
   }
   return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
 }
@@ -471,7 +506,11 @@ PSF_API psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   psf::DevStats d;
+  std::vector<psf::BlockTouch> bt(psf::kTouchEntries);
   hipError_t e = hipMemcpyAsync(&d, t->tv.stats, sizeof d, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bt.data(), t->tv.touch, bt.size() * sizeof(psf::BlockTouch),
+                       hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "read statistics");
   uint64_t occ = 0;
@@ -482,9 +521,11 @@ PSF_API psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream
   out->skipped = d.skipped;
   out->dropped = d.dropped;
   out->coord_overflow = d.coord_overflow;
-  out->touched_last = d.touched_last;
-  out->touched_total = d.touched_total;
-  out->updates = d.updates;
+  for (uint32_t i = 0; i < psf::kTouchEntries; ++i) {
+    if (i < t->touch_entries) out->touched_last += bt[i].last;
+    out->touched_total += bt[i].total;
+  }
+  out->updates = t->updates;
   out->saturated = d.saturated;
   out->occupied = occ;
   for (int i = 0; i < 16; ++i) out->probe_hist[i] = d.probe_hist[i];

@@ -39,29 +39,34 @@ struct alignas(16) Acc {
   float s[3];
 };
 
-// Device-resident counters.
+// Device-resident counters of rare events (one atomic per wave or block
+// when non-zero).
 struct alignas(256) DevStats {
   unsigned long long skipped;
   unsigned long long dropped;
   unsigned long long coord_overflow;
-  unsigned long long touched_last;
-  unsigned long long touched_total;
-  unsigned long long updates;
   unsigned long long saturated;
   unsigned long long probe_hist[16];
-  uint32_t touched_count;  // cells blended by the running update
-  uint32_t done_blocks;    // completion counter of the update kernel
-  uint32_t query_skipped;
-  uint32_t pad;
 };
+
+// Per-block count of blended cells, written by the block that owns the entry
+// (no shared counters on the hot path).
+struct alignas(16) BlockTouch {
+  uint32_t last;
+  uint32_t pad;
+  unsigned long long total;
+};
+constexpr uint32_t kTouchEntries = 8192;
 
 // View of one table handed to kernels by value.
 struct TableView {
   Slot* slots;
+  unsigned long long* keys;  // mirror of slots[].key, read by the partitioned merge
   Acc* acc;
   DevStats* stats;
+  BlockTouch* touch;         // kTouchEntries
   uint32_t log2_slots;
-  uint32_t part_log2;   // slots per partition = 2^part_log2 (<= log2_slots)
+  uint32_t part_log2;        // slots per partition = 2^part_log2 (<= log2_slots)
   uint32_t max_probe;
   uint32_t flags;
 };

@@ -19,10 +19,11 @@ struct QryPtrs {
 
 // Partitioned-insert working buffers of one table.
 struct PartView {
-  unsigned long long* stage_key;  // staged keys, grouped per tile by partition
-  float* stage_rgb;               // 3 x capacity, SoA
+  unsigned long long* stage_key;  // staged sample keys, grouped per tile by partition
+  float* stage_rgb;               // staged sample values (r, g, b triples), same order
   uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile
-  uint32_t tile;                  // records per binning tile (<= 65535)
+  unsigned long long* rkeys;      // key of every record of the last binning, record order
+  uint32_t tile;                  // records per binning tile
   uint32_t max_tiles;             // tiles per launch
   uint64_t capacity;              // records per launch
 };
@@ -46,6 +47,12 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
                       const PartView& pv, hipStream_t s);
 hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
                         hipStream_t s);
+// Lookup of the records binned last, by their cached keys.
+hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, const TableView& tv,
+                               int32_t dtype, float* out, uint8_t* found, hipStream_t s);
+bool bin_per_ok(uint32_t per);          // supported records per thread of the binning pass
+uint32_t bin_tile(uint32_t per);        // records per binning tile
+uint32_t update_grid(uint64_t nslots);  // blocks of the streaming update
 hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);

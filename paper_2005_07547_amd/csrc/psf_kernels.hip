@@ -31,7 +31,10 @@ __device__ __forceinline__ uint64_t find_or_claim(const TableView& tv, uint64_t 
     const uint64_t s = ps.at(i);
     unsigned long long* kp = &tv.slots[s].key;
     unsigned long long cur = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == kEmpty) cur = atomicCAS(kp, kEmpty, (unsigned long long)key);
+    if (cur == kEmpty) {
+      cur = atomicCAS(kp, kEmpty, (unsigned long long)key);
+      if (cur == kEmpty) tv.keys[s] = key;  // this lane claimed the slot
+    }
     if (cur == kEmpty || cur == key) {
       *probes = i + 1;
       return s;
@@ -178,8 +181,8 @@ __device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParam
   return true;
 }
 
-// Streaming pass over every slot's accumulator; the last block to finish
-// publishes the number of cells blended.
+// Streaming pass over every slot's accumulator; each block records how many
+// cells it blended in its own BlockTouch entry.
 __global__ void __launch_bounds__(256) k_update(TableView tv, BlendParams bp, uint64_t nslots) {
   __shared__ uint32_t s_touched, s_sat;
   if (threadIdx.x == 0) s_touched = s_sat = 0;
@@ -195,19 +198,9 @@ __global__ void __launch_bounds__(256) k_update(TableView tv, BlendParams bp, ui
   __syncthreads();
   if (threadIdx.x == 0) {
     if (s_sat) atomicAdd(&tv.stats->saturated, (unsigned long long)s_sat);
-    if (s_touched) atomicAdd(&tv.stats->touched_count, s_touched);
-    __threadfence();
-    const uint32_t done = atomicAdd(&tv.stats->done_blocks, 1u);
-    if (done == gridDim.x - 1) {
-      const uint32_t cnt = __hip_atomic_load(&tv.stats->touched_count, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-      tv.stats->touched_last = cnt;
-      tv.stats->touched_total += cnt;
-      tv.stats->updates += 1;
-      tv.stats->touched_count = 0;
-      tv.stats->done_blocks = 0;
-      __threadfence();
-    }
+    BlockTouch* bt = &tv.touch[blockIdx.x];
+    bt->last = s_touched;
+    bt->total += s_touched;
   }
 }
 
@@ -250,11 +243,8 @@ __global__ void k_clear(TableView tv, uint64_t nslots) {
     z.pad = 0;
     z.L[0] = z.L[1] = z.L[2] = z.L[3] = 0;
     tv.slots[s] = z;
+    tv.keys[s] = kEmpty;
     tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    tv.stats->touched_count = 0;
-    tv.stats->done_blocks = 0;
   }
 }
 
@@ -271,13 +261,19 @@ __global__ void k_zero_words(uint32_t* p, uint64_t words) {
 }
 
 // ------------------------------------------------------------------ export support
-__global__ void k_count_occupied(TableView tv, uint64_t nslots, unsigned long long* out) {
+__global__ void __launch_bounds__(256) k_count_occupied(TableView tv, uint64_t nslots,
+                                                        unsigned long long* out) {
+  __shared__ uint32_t s_c;
+  if (threadIdx.x == 0) s_c = 0;
+  __syncthreads();
   uint32_t c = 0;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
        s += (uint64_t)gridDim.x * blockDim.x)
-    c += tv.slots[s].key != kEmpty;
+    c += tv.keys[s] != kEmpty;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+  if (lane_id() == 0 && c) atomicAdd(&s_c, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_c) atomicAdd(out, (unsigned long long)s_c);
 }
 
 __global__ void k_compact(TableView tv, uint64_t nslots, int32_t dtype, unsigned long long* cursor,
@@ -324,8 +320,10 @@ hipError_t launch_insert_direct(const RecPtrs& rec, uint64_t n, const KeyParams&
   return hipGetLastError();
 }
 
+uint32_t update_grid(uint64_t nslots) { return stride_grid(nslots, 256, 2048); }
+
 hipError_t launch_update(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s) {
-  k_update<<<stride_grid(nslots, 256, 2048), 256, 0, s>>>(tv, bp, nslots);
+  k_update<<<update_grid(nslots), 256, 0, s>>>(tv, bp, nslots);
   return hipGetLastError();
 }
 
@@ -353,7 +351,7 @@ hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s) {
 
 hipError_t launch_count_occupied(const TableView& tv, uint64_t nslots, unsigned long long* out,
                                  hipStream_t s) {
-  k_count_occupied<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, out);
+  k_count_occupied<<<stride_grid(nslots, 256, 512), 256, 0, s>>>(tv, nslots, out);
   return hipGetLastError();
 }
 

@@ -6,17 +6,17 @@
 // key is the top bits of its hash, its probe sequence stays inside the
 // partition).  Insertion then runs in two passes:
 //
-//   bin   -- one 1024-thread block per tile of records computes the keys,
-//            counts records per partition in LDS and writes (key, rgb) to a
-//            staging area grouped by partition inside the tile, plus the
-//            tile's exclusive per-partition offsets;
+//   bin   -- one block per tile of records computes the keys, counts records
+//            per partition in LDS, sorts the tile by partition in LDS and
+//            writes it out coalesced (keys, then rgb triples) to a staging
+//            area, plus the tile's exclusive per-partition offsets;
 //   merge -- one block per partition loads the partition's keys into LDS,
-//            gathers that partition's staged entries from every tile, finds
-//            or claims each key's slot and accumulates count and sums with
-//            LDS atomics, then writes the partition back: either adding into
-//            the global accumulators (plain insert) or, when the whole frame
-//            is in this launch, applying the temporal blend (Eq. 10-11)
-//            directly so the accumulators never touch HBM.
+//            gathers that partition's entries from every tile, finds or
+//            claims each key's slot and accumulates count and sums with LDS
+//            atomics, then writes the partition back: either adding into the
+//            global accumulators (plain insert) or, when the whole frame is in
+//            this launch, applying the temporal blend (Eq. 10-11) directly so
+//            the accumulators never touch HBM.
 //
 // A partition is owned by exactly one block in the merge pass, so the
 // write-back uses plain loads and stores.
@@ -25,32 +25,84 @@
 
 namespace psf {
 
-constexpr int kBinThreads = 1024;
-constexpr uint32_t kBinPer = 8;  // records per thread; a tile is kBinThreads * kBinPer
+constexpr int kBinThreads = 512;
 constexpr int kMergeThreads = 512;
 constexpr uint32_t kMaxPartLog2 = 12;
 
+bool bin_per_ok(uint32_t per) { return per == 8 || per == 12 || per == 16; }
+uint32_t bin_tile(uint32_t per) { return kBinThreads * per; }
+
+// Exclusive prefix sum of cnt[0..m) in LDS, in place; returns the total.
+// Called by all kThreads threads of the block.
+template <int kThreads>
+__device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_wave) {
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+  const uint32_t chunk = (m + kThreads - 1) / kThreads;
+  const uint32_t lo = tid * chunk;
+  uint32_t local = 0;
+  for (uint32_t c = 0; c < chunk; ++c)
+    if (lo + c < m) local += cnt[lo + c];
+  // inclusive scan across the wave
+  uint32_t inc = local;
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(inc, off);
+    if (lane >= off) inc += v;
+  }
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const uint32_t v = s_wave[w];
+      s_wave[w] = run;
+      run += v;
+    }
+    s_wave[kThreads / 64] = run;
+  }
+  __syncthreads();
+  uint32_t run = s_wave[wave] + inc - local;
+  for (uint32_t c = 0; c < chunk; ++c) {
+    if (lo + c < m) {
+      const uint32_t v = cnt[lo + c];
+      cnt[lo + c] = run;
+      run += v;
+    }
+  }
+  const uint32_t total = s_wave[kThreads / 64];
+  __syncthreads();
+  return total;
+}
+
 // ------------------------------------------------------------------ bin
+// Dynamic LDS holds first the partition histogram (P + 1 words), then, once
+// every record knows its place, the tile's staging buffer (tile * 12 bytes:
+// keys, then rgb triples), so that both global writes of the partition-
+// sorted tile are coalesced.
+template <uint32_t kPer>
 __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
                                                      TableView tv, PartView pv) {
-  extern __shared__ uint32_t s_hist[];  // P + 1 counters
+  extern __shared__ uint32_t s_dyn_bin[];
+  __shared__ uint32_t s_wave[kBinThreads / 64 + 1];
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
+  uint32_t* s_hist = s_dyn_bin;
+  unsigned long long* s_k = reinterpret_cast<unsigned long long*>(s_dyn_bin);
+  float* s_f = reinterpret_cast<float*>(s_dyn_bin);
   const uint32_t tid = threadIdx.x;
   const uint32_t tile = blockIdx.x;
-  const uint64_t t0 = (uint64_t)tile * pv.tile;
+  const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
   for (uint32_t p = tid; p <= P; p += kBinThreads) s_hist[p] = 0;
   __syncthreads();
 
-  uint64_t key[kBinPer];
-  uint32_t part_rank[kBinPer];  // partition << 16 | rank, or ~0 if not staged
-  float rgb[kBinPer][3];
+  uint64_t key[kPer];
+  uint32_t pos[kPer];  // partition << 16 | rank, then the slot in the sorted tile; ~0 if unused
+  float rgb[kPer][3];
   uint32_t n_skip = 0, n_ovf = 0;
+  const bool hr = rec.rough != nullptr;
 #pragma unroll
-  for (uint32_t j = 0; j < kBinPer; ++j) {
-    part_rank[j] = ~0u;
+  for (uint32_t j = 0; j < kPer; ++j) {
+    pos[j] = ~0u;
     const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
     if (i >= n) continue;
-    const bool hr = rec.rough != nullptr;
     const float ro = hr ? rec.rough[i] : 0.0f;
     const bool gl = hr && ro < kp.rough_thr;
     const float r = rec.r[i], g = rec.g[i], b = rec.b[i];
@@ -60,6 +112,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
                        gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro,
                        k, ovf);
     ok = ok && finite3(r, g, b);
+    if (pv.rkeys) pv.rkeys[i] = ok ? k : kEmpty;
     if (!ok) {
       ++n_skip;
       continue;
@@ -68,7 +121,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
     const uint32_t p = partition_of(fmix64(k), tv.log2_slots, tv.part_log2);
     const uint32_t rank = atomicAdd(&s_hist[p], 1u);
     key[j] = k;
-    part_rank[j] = (p << 16) | rank;
+    pos[j] = (p << 16) | rank;
     rgb[j][0] = r;
     rgb[j][1] = g;
     rgb[j][2] = b;
@@ -83,60 +136,57 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
     if (n_ovf) atomicAdd(&tv.stats->coord_overflow, (unsigned long long)n_ovf);
   }
   __syncthreads();
-
-  // exclusive scan of the P+1 counters (last one stays 0 -> becomes total)
-  __shared__ uint32_t s_part[kBinThreads];
-  const uint32_t cnt_total = P + 1;
-  const uint32_t chunk = (cnt_total + kBinThreads - 1) / kBinThreads;
-  const uint32_t lo = tid * chunk;
-  uint32_t local = 0;
-  for (uint32_t c = 0; c < chunk; ++c)
-    if (lo + c < cnt_total) local += s_hist[lo + c];
-  s_part[tid] = local;
-  __syncthreads();
-  for (uint32_t off = 1; off < kBinThreads; off <<= 1) {
-    const uint32_t v = tid >= off ? s_part[tid - off] : 0u;
-    __syncthreads();
-    s_part[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run = s_part[tid] - local;  // exclusive prefix of this chunk
-  for (uint32_t c = 0; c < chunk; ++c) {
-    if (lo + c < cnt_total) {
-      const uint32_t v = s_hist[lo + c];
-      s_hist[lo + c] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
+  const uint32_t count = block_exclusive_scan<kBinThreads>(s_hist, P + 1, s_wave);
 
   uint32_t* offs = pv.runs + (uint64_t)tile * (P + 1);
   for (uint32_t p = tid; p <= P; p += kBinThreads) offs[p] = s_hist[p];
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (pos[j] != ~0u) pos[j] = s_hist[pos[j] >> 16] + (pos[j] & 0xffffu);
+  __syncthreads();  // the histogram is dead from here on; its LDS becomes staging
 
 #pragma unroll
-  for (uint32_t j = 0; j < kBinPer; ++j) {
-    if (part_rank[j] == ~0u) continue;
-    const uint64_t pos = t0 + s_hist[part_rank[j] >> 16] + (part_rank[j] & 0xffffu);
-    pv.stage_key[pos] = key[j];
-    pv.stage_rgb[pos] = rgb[j][0];
-    pv.stage_rgb[pv.capacity + pos] = rgb[j][1];
-    pv.stage_rgb[2 * pv.capacity + pos] = rgb[j][2];
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (pos[j] != ~0u) s_k[pos[j]] = key[j];
+  __syncthreads();
+  for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_key[t0 + i] = s_k[i];
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    if (pos[j] == ~0u) continue;
+    s_f[3 * pos[j] + 0] = rgb[j][0];
+    s_f[3 * pos[j] + 1] = rgb[j][1];
+    s_f[3 * pos[j] + 2] = rgb[j][2];
   }
+  __syncthreads();
+  float* dst = pv.stage_rgb + 3 * t0;
+  for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
 }
 
 // ------------------------------------------------------------------ merge
-// bp == nullptr: add into the global accumulators; otherwise blend.
+// Blocks are dispatched to the 8 XCDs round-robin; give each XCD a
+// contiguous range of partitions so the offset rows they share stay in one
+// L2.
+__device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P) {
+  if (P < 8 || (P & 7u)) return b;
+  return (b & 7u) * (P >> 3) + (b >> 3);
+}
+
+constexpr uint32_t kMergeBatch = 4;  // consecutive entries per thread, loaded before processing
+
 template <bool kFused>
 __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles,
                                                          BlendParams bp) {
   extern __shared__ unsigned long long s_dyn[];  // key[B] | cnt[B] | sum[3][B]
-  __shared__ uint32_t s_scan[kMergeThreads];
+  __shared__ uint32_t s_start[kMergeThreads + 1];  // exclusive prefix of run lengths, then total
+  __shared__ uint32_t s_lo[kMergeThreads];         // offset of each run inside its tile
+  __shared__ uint32_t s_wave[kMergeThreads / 64 + 1];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t B = 1u << tv.part_log2;
-  const uint32_t p = blockIdx.x;
+  const uint32_t p = xcd_partition(blockIdx.x, P);
   const uint64_t base = (uint64_t)p << tv.part_log2;
   const bool stats = (tv.flags & 1u) != 0;
   unsigned long long* s_key = s_dyn;
@@ -146,69 +196,78 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
   float* s_sum2 = s_sum1 + B;
 
   for (uint32_t s = tid; s < B; s += kMergeThreads) {
-    s_key[s] = tv.slots[base + s].key;
+    s_key[s] = tv.keys[base + s];
     s_cnt[s] = 0;
     s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0f;
   }
   if (tid == 0) s_dropped = s_touched = s_sat = 0;
   if (tid < 16) s_hist[tid] = 0;
 
-  // per-tile run lengths of this partition, scanned so entries can be
-  // spread evenly over the block (tiles are processed kMergeThreads at a time)
-  for (uint32_t t0 = 0; t0 < ntiles; t0 += kMergeThreads) {
-    const uint32_t t = t0 + tid;
-    uint32_t lo = 0, len = 0;
-    if (t < ntiles) {
-      const uint32_t* offs = pv.runs + (uint64_t)t * (P + 1);
-      lo = offs[p];
-      len = offs[p + 1] - lo;
+  const uint32_t tile = pv.tile;
+  for (uint32_t c0 = 0; c0 < ntiles; c0 += kMergeThreads) {
+    // run of this partition in tile c0 + tid
+    uint32_t len = 0, lo = 0;
+    if (c0 + tid < ntiles) {
+      const uint32_t* offs = pv.runs + (uint64_t)(c0 + tid) * (P + 1) + p;
+      lo = offs[0];
+      len = offs[1] - lo;
     }
+    __syncthreads();  // previous chunk done with s_start / s_lo
+    s_start[tid] = len;
+    s_lo[tid] = lo;
+    const uint32_t total = block_exclusive_scan<kMergeThreads>(s_start, kMergeThreads, s_wave);
+    if (tid == 0) s_start[kMergeThreads] = total;
     __syncthreads();
-    s_scan[tid] = len;
-    __syncthreads();
-    for (uint32_t off = 1; off < kMergeThreads; off <<= 1) {
-      const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    const uint32_t total = s_scan[kMergeThreads - 1];
-    // entry e belongs to the tile whose inclusive prefix first exceeds e
-    for (uint32_t e = tid; e < total; e += kMergeThreads) {
+
+    for (uint32_t e0 = tid * kMergeBatch; e0 < total; e0 += kMergeThreads * kMergeBatch) {
+      // run holding e0: the last run whose start is <= e0 (empty runs share
+      // their start with the next run, so the last one is the non-empty one)
       uint32_t a = 0, b = kMergeThreads - 1;
       while (a < b) {
-        const uint32_t m = (a + b) >> 1;
-        if (s_scan[m] > e) b = m; else a = m + 1;
+        const uint32_t m = (a + b + 1) >> 1;
+        if (s_start[m] <= e0) a = m; else b = m - 1;
       }
-      const uint32_t tt = t0 + a;
-      const uint32_t before = a ? s_scan[a - 1] : 0u;
-      const uint32_t* offs = pv.runs + (uint64_t)tt * (P + 1);
-      const uint64_t pos = (uint64_t)tt * pv.tile + offs[p] + (e - before);
-      const unsigned long long key = pv.stage_key[pos];
-      const float r = pv.stage_rgb[pos];
-      const float g = pv.stage_rgb[pv.capacity + pos];
-      const float b2 = pv.stage_rgb[2 * pv.capacity + pos];
-      const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
-      uint32_t slot = ~0u;
-      uint32_t i = 0;
-      for (; i < tv.max_probe; ++i) {
-        const uint32_t s = (start + i) & (B - 1);
-        unsigned long long cur = s_key[s];
-        if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
-        if (cur == kEmpty || cur == key) {
-          slot = s;
-          break;
+      unsigned long long ek[kMergeBatch];
+      float er[kMergeBatch], eg[kMergeBatch], eb[kMergeBatch];
+      bool ev[kMergeBatch];
+#pragma unroll
+      for (uint32_t q = 0; q < kMergeBatch; ++q) {
+        const uint32_t e = e0 + q;
+        ev[q] = e < total;
+        if (!ev[q]) continue;
+        while (s_start[a + 1] <= e) ++a;
+        const uint64_t at = (uint64_t)(c0 + a) * tile + s_lo[a] + (e - s_start[a]);
+        ek[q] = pv.stage_key[at];
+        er[q] = pv.stage_rgb[3 * at];
+        eg[q] = pv.stage_rgb[3 * at + 1];
+        eb[q] = pv.stage_rgb[3 * at + 2];
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kMergeBatch; ++q) {
+        if (!ev[q]) continue;
+        const unsigned long long key = ek[q];
+        const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
+        uint32_t slot = ~0u;
+        uint32_t i = 0;
+        for (; i < tv.max_probe; ++i) {
+          const uint32_t s = (start + i) & (B - 1);
+          unsigned long long cur = s_key[s];
+          if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
+          if (cur == kEmpty || cur == key) {
+            slot = s;
+            break;
+          }
         }
+        if (slot == ~0u) {
+          atomicAdd(&s_dropped, 1u);
+          continue;
+        }
+        if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
+        atomicAdd(&s_cnt[slot], 1u);
+        atomicAdd(&s_sum0[slot], er[q]);
+        atomicAdd(&s_sum1[slot], eg[q]);
+        atomicAdd(&s_sum2[slot], eb[q]);
       }
-      if (slot == ~0u) {
-        atomicAdd(&s_dropped, 1u);
-        continue;
-      }
-      if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
-      atomicAdd(&s_cnt[slot], 1u);
-      atomicAdd(&s_sum0[slot], r);
-      atomicAdd(&s_sum1[slot], g);
-      atomicAdd(&s_sum2[slot], b2);
     }
   }
   __syncthreads();
@@ -221,23 +280,31 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
     if (c == 0) continue;
     const uint64_t g = base + s;
     Slot* d = &tv.slots[g];
+    const unsigned long long k = s_key[s];
     if (kFused) {
-      const uint32_t c_old = d->c_old;
-      const float alpha = blend_alpha(bp, c, c_old);
+      const Slot old = *d;
+      const float alpha = blend_alpha(bp, c, old.c_old);
       const float inv = 1.0f / (float)c;
       float L[3];
-      load_state(*d, bp.dtype, L[0], L[1], L[2]);
-      float out[3];
+      load_state(old, bp.dtype, L[0], L[1], L[2]);
       const float sums[3] = {s_sum0[s], s_sum1[s], s_sum2[s]};
+      float out[3];
       for (int ch = 0; ch < 3; ++ch) {
         const float m = sums[ch] * inv;
         out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
       }
       uint32_t enc[4];
       encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
-      d->key = s_key[s];
-      d->c_old = c_old + c;
-      *reinterpret_cast<uint4*>(d->L) = make_uint4(enc[0], enc[1], enc[2], enc[3]);
+      Slot nw;
+      nw.key = k;
+      nw.c_old = old.c_old + c;
+      nw.pad = 0;
+      nw.L[0] = enc[0];
+      nw.L[1] = enc[1];
+      nw.L[2] = enc[2];
+      nw.L[3] = enc[3];
+      *d = nw;
+      if (old.key != k) tv.keys[g] = k;
       ++touched;
     } else {
       Acc a = tv.acc[g];
@@ -246,7 +313,10 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
       a.s[1] += s_sum1[s];
       a.s[2] += s_sum2[s];
       tv.acc[g] = a;
-      d->key = s_key[s];
+      if (d->key != k) {
+        d->key = k;
+        tv.keys[g] = k;
+      }
     }
   }
   if (kFused) {
@@ -259,49 +329,92 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
     if (s_dropped) atomicAdd(&tv.stats->dropped, (unsigned long long)s_dropped);
     if (kFused) {
       if (s_sat) atomicAdd(&tv.stats->saturated, (unsigned long long)s_sat);
-      if (s_touched) atomicAdd(&tv.stats->touched_count, s_touched);
-      __threadfence();
-      const uint32_t done = atomicAdd(&tv.stats->done_blocks, 1u);
-      if (done == gridDim.x - 1) {
-        const uint32_t cnt = __hip_atomic_load(&tv.stats->touched_count, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        tv.stats->touched_last = cnt;
-        tv.stats->touched_total += cnt;
-        tv.stats->updates += 1;
-        tv.stats->touched_count = 0;
-        tv.stats->done_blocks = 0;
-        __threadfence();
-      }
+      BlockTouch* bt = &tv.touch[blockIdx.x];
+      bt->last = s_touched;
+      bt->total += s_touched;
     }
   }
   if (stats && tid < 16 && s_hist[tid])
     atomicAdd(&tv.stats->probe_hist[tid], (unsigned long long)s_hist[tid]);
 }
 
-static hipError_t merge_attr() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  const int lim = (int)((size_t)(1u << kMaxPartLog2) * (8 + 4 + 12));
-  hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_merge<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (a == hipSuccess)
-    a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_merge<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (a == hipSuccess) done = true;
-  return a;
+// ------------------------------------------------------------------ cached-key lookup
+__global__ void __launch_bounds__(256) k_query_cached(const unsigned long long* rkeys, uint64_t n,
+                                                      TableView tv, int32_t dtype, float* out,
+                                                      uint8_t* found) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long key = rkeys[i];
+  float r = 0.0f, g = 0.0f, b = 0.0f;
+  uint8_t hit = 0;
+  if (key != kEmpty) {
+    const ProbeSeq ps = probe_seq(key, tv.log2_slots, tv.part_log2);
+    for (uint32_t j = 0; j < tv.max_probe; ++j) {
+      const Slot sl = tv.slots[ps.at(j)];
+      if (sl.key == key) {
+        if (sl.c_old > 0) {
+          load_state(sl, dtype, r, g, b);
+          hit = 1;
+        }
+        break;
+      }
+      if (sl.key == kEmpty) break;
+    }
+  }
+  out[i] = r;
+  out[n + i] = g;
+  out[2 * n + i] = b;
+  if (found) found[i] = hit;
 }
 
-bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
-  return n <= pv.capacity && tv.part_log2 <= kMaxPartLog2 && pv.tile == kBinThreads * kBinPer;
+// ------------------------------------------------------------------ launchers
+static size_t bin_lds(uint32_t P, uint32_t per) {
+  const size_t hist = (size_t)(P + 1) * 4, stage = (size_t)kBinThreads * per * 12;
+  return hist > stage ? hist : stage;
+}
+
+static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 12); }
+
+static hipError_t kernel_attrs() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const int lim_m = (int)merge_lds(kMaxPartLog2);
+  const void* fns[] = {reinterpret_cast<const void*>(&k_merge<true>),
+                       reinterpret_cast<const void*>(&k_merge<false>),
+                       reinterpret_cast<const void*>(&k_bin<8>),
+                       reinterpret_cast<const void*>(&k_bin<12>),
+                       reinterpret_cast<const void*>(&k_bin<16>)};
+  const int lims[] = {lim_m, lim_m, (int)bin_lds(kTouchEntries, 8), (int)bin_lds(kTouchEntries, 12),
+                      (int)bin_lds(kTouchEntries, 16)};
+  for (int i = 0; i < 5; ++i) {
+    hipError_t a = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i]);
+    if (a != hipSuccess) return a;
+  }
+  done = true;
+  return hipSuccess;
+}
+
+static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
+  return n <= pv.capacity && tv.part_log2 <= kMaxPartLog2 && pv.tile % kBinThreads == 0 &&
+         bin_per_ok(pv.tile / kBinThreads) && (1u << (tv.log2_slots - tv.part_log2)) <= kTouchEntries;
 }
 
 hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
                       const PartView& pv, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
+  hipError_t e = kernel_attrs();
+  if (e != hipSuccess) return e;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
+  const uint32_t per = pv.tile / kBinThreads;
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
-  k_bin<<<ntiles, kBinThreads, (size_t)(P + 1) * sizeof(uint32_t), s>>>(rec, n, kp, tv, pv);
+  const size_t shm = bin_lds(P, per);
+  if (per == 8)
+    k_bin<8><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
+  else if (per == 12)
+    k_bin<12><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
+  else
+    k_bin<16><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
   return hipGetLastError();
 }
 
@@ -309,15 +422,22 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
                         hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
-  hipError_t e = merge_attr();
+  hipError_t e = kernel_attrs();
   if (e != hipSuccess) return e;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
-  const size_t shm = (size_t)(1u << tv.part_log2) * (8 + 4 + 12);
+  const size_t shm = merge_lds(tv.part_log2);
   if (fuse)
     k_merge<true><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse);
   else
     k_merge<false><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, BlendParams{});
+  return hipGetLastError();
+}
+
+hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, const TableView& tv,
+                               int32_t dtype, float* out, uint8_t* found, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_query_cached<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rkeys, n, tv, dtype, out, found);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ class psf_config(ctypes.Structure):
         ("alpha_mode", ctypes.c_int32), ("alpha", ctypes.c_float), ("t_max", ctypes.c_float),
         ("state_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("insert_mode", ctypes.c_int32), ("part_log2", ctypes.c_uint32),
-        ("max_batch", ctypes.c_uint64),
+        ("max_batch", ctypes.c_uint64), ("bin_per", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -123,7 +123,8 @@ def _check(status):
 def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0,
                 max_level=15, normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
                 alpha_mode=PSF_ALPHA_PAPER, alpha=0.2, t_max=5.0, state_dtype=PSF_STATE_F32,
-                flags=0, insert_mode=PSF_INSERT_AUTO, part_log2=0, max_batch=0, **_ignored):
+                flags=0, insert_mode=PSF_INSERT_AUTO, part_log2=0, max_batch=0, bin_per=0,
+                **_ignored):
     c = psf_config()
     c.log2_slots, c.max_probe = int(log2_slots), int(max_probe)
     c.cam[:] = [float(x) for x in cam]
@@ -131,7 +132,7 @@ def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_m
     c.normal_bins_log2, c.dir_bins_log2 = int(normal_bins_log2), int(dir_bins_log2)
     c.rough_thr, c.alpha_mode, c.alpha, c.t_max = float(rough_thr), int(alpha_mode), float(alpha), float(t_max)
     c.state_dtype, c.flags, c.insert_mode = int(state_dtype), int(flags), int(insert_mode)
-    c.part_log2, c.max_batch = int(part_log2), int(max_batch)
+    c.part_log2, c.max_batch, c.bin_per = int(part_log2), int(max_batch), int(bin_per)
     return c
 
 

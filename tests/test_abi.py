@@ -53,5 +53,5 @@ def test_struct_sizes_match_header():
     from paper_2005_07547_amd import psf
     assert ctypes.sizeof(psf.psf_records) == 13 * 8
     assert ctypes.sizeof(psf.psf_queries) == 10 * 8
-    assert ctypes.sizeof(psf.psf_config) == 80
+    assert ctypes.sizeof(psf.psf_config) == 88
     assert ctypes.sizeof(psf.psf_stats) == 25 * 8

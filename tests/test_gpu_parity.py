@@ -376,3 +376,29 @@ def test_invalid_arguments(psf, torch_cuda):
                dict(dir_bins_log2=4), dict(state_dtype=3), dict(part_log2=5), dict(max_probe=0)):
         c = psf.make_config(log2_slots=10, **kw)
         assert lib.psf_table_bytes(ctypes.byref(c)) == 0, kw
+
+
+@pytest.mark.parametrize("bin_per", [8, 12, 16])
+@pytest.mark.parametrize("part_log2", [8, 10, 12])
+def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_log2):
+    """Every launch configuration the autotuner may pick gives the oracle's
+    result (two fused iterations of the plain scene at reduced resolution)."""
+    from synth import workloads as W
+    wl = W.plain()
+    g = dict(wl["gen"], width=320, height=180)
+    sc = W.make_scene(wl)
+    # 2^20 slots keep every partition far from full even at 256 slots each
+    cfg = dict(wl["table"], log2_slots=20)
+    orc = _oracle(cfg)
+    t = _table(psf, cfg, insert_mode=2, bin_per=bin_per, part_log2=part_log2)
+    for it in range(2):
+        rec = sc.generate(g, it)
+        orc.insert(rec)
+        orc.update()
+        out, found = t.iterate(to_device(rec))
+    torch_cuda.cuda.synchronize()
+    assert t.stats()["dropped"] == 0
+    compare_cells(t.export(), orc.export(), RTOL_F32, f"bin_per={bin_per} part_log2={part_log2}")
+    w_out, w_found = orc.query(rec)
+    assert np.array_equal(found.cpu().numpy(), w_found)
+    assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
