@@ -135,7 +135,7 @@ typedef struct psf_config {
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M); larger inserts are split */
   uint32_t bin_per;          /* partitioned insert: records per thread of the
-                                binning pass (0 = default 16, else 8, 12, 16);
+                                binning pass (0 = default 8, else 8, 12, 16);
                                 a binning tile is 512 * bin_per records */
   uint32_t reserved;         /* must be 0 */
 } psf_config;
@@ -233,9 +233,16 @@ psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream);
 psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
                             float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
 
-/* Batched form: one iteration (insert, update, query) of k independent
- * sessions in a single persistent launch.  Each session's result equals
- * the same session run alone. */
+/* Batched form: one iteration (insert, temporal update, query) of k
+ * independent sessions, each with its own table, in three launches that
+ * cover every session (binning, merge + blend, lookup).  Each session's
+ * result equals the same session run alone through psf_iterate.  Sessions
+ * that cannot join the batch (direct insert strategy, samples pending from
+ * psf_insert_samples, n above the table's max_batch, a binning width
+ * different from the first batchable session's) run through psf_iterate
+ * first, on the same stream.  d_out_rgb (3*nq floats, SoA) and d_out_found
+ * (nullable) as in psf_query; queries equal to the records (the same
+ * arrays) reuse the keys computed while binning. */
 typedef struct psf_session {
   psf_table* table;
   psf_records rec;
@@ -246,7 +253,23 @@ typedef struct psf_session {
   uint8_t* d_out_found;
 } psf_session;
 
-psf_status psf_iterate_batch(const psf_session* sessions, uint32_t k, psf_stream stream);
+/* A batch context owns the session descriptors of batched calls: a pinned
+ * host copy and a device copy of up to max_sessions entries.  A call made
+ * during HIP stream capture records a copy from the pinned buffer, so a
+ * context used in a captured graph must not be used for other calls while
+ * the graph is replayed (use one context per graph).  Outside capture, a
+ * call waits for the context's previous descriptor copy before reusing the
+ * pinned buffer.  Host-side statistics (submitted, updates) count calls,
+ * not graph replays. */
+typedef struct psf_batch psf_batch;
+
+psf_status psf_batch_create(uint32_t max_sessions, psf_batch** out);
+
+/* Synchronises the context's last descriptor copy and frees it; NULL is a
+ * no-op. */
+psf_status psf_batch_destroy(psf_batch* b);
+
+psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, uint32_t k, psf_stream stream);
 
 /* Per-kernel timing (tables created with PSF_FLAG_TIMING): for each kernel
  * kind k < PSF_K_COUNT, launches[k] and total_ms[k] (host arrays of

@@ -111,7 +111,7 @@ hipError_t timed(psf_table* t, int kind, hipStream_t s, F&& launch) {
 }
 
 constexpr uint32_t kDefaultPartLog2 = 11;
-constexpr uint32_t kDefaultBinPer = 16;
+constexpr uint32_t kDefaultBinPer = 8;
 constexpr uint64_t kDefaultBatch = 1ull << 22;
 constexpr uint32_t kMaxPartitions = 1u << 13;  // LDS histogram of the binning pass
 
@@ -569,14 +569,128 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
   return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
 }
 
-PSF_API psf_status psf_iterate_batch(const psf_session* sessions, uint32_t k, psf_stream stream) {
+struct psf_batch {
+  uint32_t cap = 0;
+  psf::BatchSession* host = nullptr;  // pinned
+  psf::BatchSession* dev = nullptr;
+  hipEvent_t copied = nullptr;
+  bool in_flight = false;
+};
+
+PSF_API psf_status psf_batch_create(uint32_t max_sessions, psf_batch** out) {
+  if (!out) return fail(PSF_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (max_sessions == 0 || max_sessions > 4096) return fail(PSF_INVALID_ARGUMENT, "max_sessions must be in [1, 4096]");
+  psf_batch* b = new (std::nothrow) psf_batch();
+  if (!b) return fail(PSF_OUT_OF_MEMORY, "host allocation failed");
+  b->cap = max_sessions;
+  const size_t bytes = sizeof(psf::BatchSession) * max_sessions;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->host), bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->dev), bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->host) (void)hipHostFree(b->host);
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+    (void)hipGetLastError();
+    return fail(PSF_OUT_OF_MEMORY, std::string("batch context: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return PSF_OK;
+}
+
+PSF_API psf_status psf_batch_destroy(psf_batch* b) {
+  if (!b) return PSF_OK;
+  hipError_t e = b->in_flight ? hipEventSynchronize(b->copied) : hipSuccess;
+  (void)hipEventDestroy(b->copied);
+  (void)hipHostFree(b->host);
+  (void)hipFree(b->dev);
+  delete b;
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "batch destroy");
+}
+
+PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, uint32_t k,
+                                     psf_stream stream) {
   if (k == 0) return PSF_OK;
-  if (!sessions) return fail(PSF_INVALID_ARGUMENT, "sessions is NULL");
+  if (!b || !sessions) return fail(PSF_INVALID_ARGUMENT, "batch context or sessions is NULL");
+  if (k > b->cap) return fail(PSF_INVALID_ARGUMENT, "more sessions than the batch context holds");
+  std::string why;
   for (uint32_t i = 0; i < k; ++i) {
     const psf_session& ss = sessions[i];
-    psf_status st = psf_iterate(ss.table, &ss.rec, ss.n, &ss.q, ss.nq, ss.d_out_rgb, ss.d_out_found,
-                                stream);
+    if (!ss.table) return fail(PSF_INVALID_ARGUMENT, "session table is NULL");
+    if (ss.n > 0 && !rec_ok(&ss.rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+    if (ss.nq > 0 && !qry_ok(&ss.q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+    if (ss.nq > 0 && !ss.d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "session output is NULL");
+    for (uint32_t j = 0; j < i; ++j)
+      if (sessions[j].table == ss.table) return fail(PSF_INVALID_ARGUMENT, "a table appears twice in one batch");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // sessions that cannot join run alone first
+  uint32_t tile = 0;
+  std::vector<uint32_t> batch;
+  for (uint32_t i = 0; i < k; ++i) {
+    const psf_session& ss = sessions[i];
+    psf_table* t = ss.table;
+    const bool ok = ss.n > 0 && t->partitioned && !t->pending && ss.n <= t->pv.capacity &&
+                    (tile == 0 || t->pv.tile == tile);
+    if (ok) {
+      tile = t->pv.tile;
+      batch.push_back(i);
+      continue;
+    }
+    psf_status st = psf_iterate(t, &ss.rec, ss.n, &ss.q, ss.nq, ss.d_out_rgb, ss.d_out_found, stream);
     if (st != PSF_OK) return st;
+  }
+  if (batch.empty()) return PSF_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return hip_fail(e, "capture query");
+  if (cap == hipStreamCaptureStatusNone && b->in_flight) {
+    e = hipEventSynchronize(b->copied);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor reuse");
+    b->in_flight = false;
+  }
+  uint32_t tiles = 0, parts = 0, qblks = 0;
+  for (uint32_t j = 0; j < batch.size(); ++j) {
+    const psf_session& ss = sessions[batch[j]];
+    psf_table* t = ss.table;
+    psf::BatchSession& d = b->host[j];
+    std::memset(&d, 0, sizeof d);
+    d.tv = t->tv;
+    d.pv = t->pv;
+    d.kp = t->kp;
+    d.bp = t->bp;
+    d.rec = rec_ptrs(&ss.rec);
+    d.n = ss.n;
+    d.nq = ss.nq;
+    if (ss.nq > 0) d.q = qry_ptrs(&ss.q);
+    d.out = ss.d_out_rgb;
+    d.found = ss.d_out_found;
+    d.cached = (ss.nq == ss.n && same_vertices(&ss.rec, &ss.q)) ? 1 : 0;
+    d.tile_begin = tiles;
+    d.ntiles = (uint32_t)((ss.n + t->pv.tile - 1) / t->pv.tile);
+    d.part_begin = parts;
+    d.nparts = 1u << (t->cfg.log2_slots - t->tv.part_log2);
+    d.qblk_begin = qblks;
+    d.nqblk = (uint32_t)((ss.nq + psf::kQueryBlock - 1) / psf::kQueryBlock);
+    tiles += d.ntiles;
+    parts += (d.nparts + 7u) & ~7u;
+    qblks += d.nqblk;
+  }
+  const uint32_t m = (uint32_t)batch.size();
+  e = hipMemcpyAsync(b->dev, b->host, sizeof(psf::BatchSession) * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && cap == hipStreamCaptureStatusNone) e = hipEventRecord(b->copied, s);
+  if (e != hipSuccess) return hip_fail(e, "batch descriptor copy");
+  b->in_flight = cap == hipStreamCaptureStatusNone;
+  e = psf::launch_batch(b->dev, b->host, m, s);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  for (uint32_t j = 0; j < m; ++j) {
+    const psf_session& ss = sessions[batch[j]];
+    psf_table* t = ss.table;
+    t->last = s;
+    t->submitted += ss.n;
+    t->updates++;
+    t->touch_entries = b->host[j].nparts;
   }
   return PSF_OK;
 }

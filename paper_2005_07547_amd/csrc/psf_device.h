@@ -248,6 +248,39 @@ __device__ __forceinline__ void encode_state(int32_t dtype, float r, float g, fl
   }
 }
 
+// Lookup of one key (kEmpty = rejected record): the approximant if the cell
+// exists and has been blended (c_old > 0), else zeros.  Returns the hit flag.
+__device__ __forceinline__ uint8_t lookup_key(const TableView& tv, int32_t dtype, uint64_t key,
+                                              float rgb[3]) {
+  rgb[0] = rgb[1] = rgb[2] = 0.0f;
+  if (key == kEmpty) return 0;
+  const ProbeSeq ps = probe_seq(key, tv.log2_slots, tv.part_log2);
+  for (uint32_t j = 0; j < tv.max_probe; ++j) {
+    const Slot sl = tv.slots[ps.at(j)];
+    if (sl.key == key) {
+      if (sl.c_old == 0) return 0;
+      load_state(sl, dtype, rgb[0], rgb[1], rgb[2]);
+      return 1;
+    }
+    if (sl.key == kEmpty) return 0;
+  }
+  return 0;
+}
+
+// Key of query i of a structure-of-arrays query set (kEmpty if rejected).
+template <class Q>
+__device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, uint64_t i) {
+  const bool hr = q.rough != nullptr;
+  const float ro = hr ? q.rough[i] : 0.0f;
+  const bool gl = hr && ro < kp.rough_thr;
+  uint64_t key;
+  bool ovf;
+  if (!cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
+                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, key, ovf))
+    return kEmpty;
+  return key;
+}
+
 // Eq. 10-11 for one cell, FP32.  n > 0.
 __device__ __forceinline__ float blend_alpha(const BlendParams& bp, uint32_t n, uint32_t c_old) {
   const float nf = (float)n;

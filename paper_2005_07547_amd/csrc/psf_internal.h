@@ -53,6 +53,30 @@ hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, cons
 bool bin_per_ok(uint32_t per);          // supported records per thread of the binning pass
 uint32_t bin_tile(uint32_t per);        // records per binning tile
 uint32_t update_grid(uint64_t nslots);  // blocks of the streaming update
+
+// One session of a batched iteration (device copy read by the batch kernels).
+struct BatchSession {
+  TableView tv;
+  PartView pv;
+  KeyParams kp;
+  BlendParams bp;
+  RecPtrs rec;
+  QryPtrs q;
+  uint64_t n, nq;
+  float* out;
+  uint8_t* found;
+  uint32_t tile_begin, ntiles;  // binning blocks
+  uint32_t part_begin, nparts;  // merge blocks (part_begin is a multiple of 8)
+  uint32_t qblk_begin, nqblk;   // query blocks
+  int32_t cached;               // queries are the binned records: use their keys
+  int32_t pad;
+};
+
+// Launch the three batch kernels for k sessions (all partition-capable, no
+// pending samples, the same binning width); d_sessions is device memory.
+hipError_t launch_batch(const BatchSession* d_sessions, const BatchSession* h_sessions, uint32_t k,
+                        hipStream_t s);
+constexpr uint32_t kQueryBlock = 256;
 hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);

@@ -209,27 +209,11 @@ __global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams 
                                                int32_t dtype, float* out, uint8_t* found) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint64_t key;
-  bool ovf;
-  const bool hr = q.rough != nullptr;
-  const float ro = hr ? q.rough[i] : 0.0f;
-  const bool gl = hr && ro < kp.rough_thr;
-  float r = 0.0f, g = 0.0f, b = 0.0f;
-  uint8_t hit = 0;
-  if (cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
-               gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, key, ovf)) {
-    const uint64_t s = find_slot(tv, key);
-    if (s != ~0ull) {
-      const Slot sl = tv.slots[s];
-      if (sl.c_old > 0) {
-        load_state(sl, dtype, r, g, b);
-        hit = 1;
-      }
-    }
-  }
-  out[i] = r;
-  out[n + i] = g;
-  out[2 * n + i] = b;
+  float rgb[3];
+  const uint8_t hit = lookup_key(tv, dtype, query_key(kp, q, i), rgb);
+  out[i] = rgb[0];
+  out[n + i] = rgb[1];
+  out[2 * n + i] = rgb[2];
   if (found) found[i] = hit;
 }
 

@@ -79,8 +79,8 @@ __device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_
 // keys, then rgb triples), so that both global writes of the partition-
 // sorted tile are coalesced.
 template <uint32_t kPer>
-__global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
-                                                     TableView tv, PartView pv) {
+__device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
+                                         const TableView& tv, const PartView& pv, uint32_t tile) {
   extern __shared__ uint32_t s_dyn_bin[];
   __shared__ uint32_t s_wave[kBinThreads / 64 + 1];
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
@@ -88,7 +88,6 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
   unsigned long long* s_k = reinterpret_cast<unsigned long long*>(s_dyn_bin);
   float* s_f = reinterpret_cast<float*>(s_dyn_bin);
   const uint32_t tid = threadIdx.x;
-  const uint32_t tile = blockIdx.x;
   const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
   for (uint32_t p = tid; p <= P; p += kBinThreads) s_hist[p] = 0;
   __syncthreads();
@@ -163,6 +162,12 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
   for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
 }
 
+template <uint32_t kPer>
+__global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
+                                                     TableView tv, PartView pv) {
+  bin_body<kPer>(rec, n, kp, tv, pv, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ merge
 // Blocks are dispatched to the 8 XCDs round-robin; give each XCD a
 // contiguous range of partitions so the offset rows they share stay in one
@@ -172,21 +177,34 @@ __device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P) {
   return (b & 7u) * (P >> 3) + (b >> 3);
 }
 
-constexpr uint32_t kMergeBatch = 4;  // consecutive entries per thread, loaded before processing
+constexpr uint32_t kRunGroups = 4;   // groups of 64 tile runs a wave keeps in registers
+constexpr uint32_t kEntryBatch = 4;  // entries per lane loaded before processing
 
+// Largest lane l with excl[l] <= e, where excl is a non-decreasing per-lane
+// value (all lanes of the wave must call this).
+__device__ __forceinline__ uint32_t wave_upper_bound(uint32_t excl, uint32_t e) {
+  uint32_t a = 0;
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+    const uint32_t v = (uint32_t)__shfl((int)excl, (int)(a + step));
+    if (a + step < 64 && v <= e) a += step;
+  }
+  return a;
+}
+
+// One partition: blk is the block's index among the partition blocks of this
+// table (the XCD-aware order maps it to a partition).
 template <bool kFused>
-__global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles,
-                                                         BlendParams bp) {
+__device__ __forceinline__ void merge_body(const TableView& tv, const PartView& pv, uint32_t ntiles,
+                                           const BlendParams& bp, uint32_t blk) {
   extern __shared__ unsigned long long s_dyn[];  // key[B] | cnt[B] | sum[3][B]
-  __shared__ uint32_t s_start[kMergeThreads + 1];  // exclusive prefix of run lengths, then total
-  __shared__ uint32_t s_lo[kMergeThreads];         // offset of each run inside its tile
-  __shared__ uint32_t s_wave[kMergeThreads / 64 + 1];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+  constexpr uint32_t kWaves = kMergeThreads / 64;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t B = 1u << tv.part_log2;
-  const uint32_t p = xcd_partition(blockIdx.x, P);
+  const uint32_t p = xcd_partition(blk, P);
   const uint64_t base = (uint64_t)p << tv.part_log2;
   const bool stats = (tv.flags & 1u) != 0;
   unsigned long long* s_key = s_dyn;
@@ -194,128 +212,172 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
   float* s_sum0 = reinterpret_cast<float*>(s_cnt + B);
   float* s_sum1 = s_sum0 + B;
   float* s_sum2 = s_sum1 + B;
+  const uint32_t tile = pv.tile;
 
-  for (uint32_t s = tid; s < B; s += kMergeThreads) {
-    s_key[s] = tv.keys[base + s];
-    s_cnt[s] = 0;
-    s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0f;
+  // Each wave owns a contiguous slice of the tiles; it keeps up to
+  // 64 * kRunGroups of this partition's runs (offset, length) in registers.
+  const uint32_t per_wave = (ntiles + kWaves - 1) / kWaves;
+  const uint32_t w_lo = wave * per_wave;
+  const uint32_t w_hi = (w_lo + per_wave < ntiles) ? w_lo + per_wave : ntiles;
+  uint32_t r_lo[kRunGroups], r_len[kRunGroups];
+  auto load_runs = [&](uint32_t g0) {
+#pragma unroll
+    for (uint32_t g = 0; g < kRunGroups; ++g) {
+      const uint32_t t = g0 + g * 64 + lane;
+      r_lo[g] = 0;
+      r_len[g] = 0;
+      if (t < w_hi) {
+        const uint32_t* offs = pv.runs + (uint64_t)t * (P + 1) + p;
+        r_lo[g] = offs[0];
+        r_len[g] = offs[1];
+      }
+    }
+  };
+
+  // keys first, then the first runs: both in flight together
+  constexpr uint32_t kKeysPerThread = (1u << kMaxPartLog2) / kMergeThreads;
+  unsigned long long kk[kKeysPerThread];
+#pragma unroll
+  for (uint32_t j = 0; j < kKeysPerThread; ++j) {
+    const uint32_t s = tid + j * kMergeThreads;
+    kk[j] = s < B ? tv.keys[base + s] : kEmpty;
+  }
+  load_runs(w_lo);
+#pragma unroll
+  for (uint32_t j = 0; j < kKeysPerThread; ++j) {
+    const uint32_t s = tid + j * kMergeThreads;
+    if (s < B) {
+      s_key[s] = kk[j];
+      s_cnt[s] = 0;
+      s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0f;
+    }
   }
   if (tid == 0) s_dropped = s_touched = s_sat = 0;
   if (tid < 16) s_hist[tid] = 0;
+  __syncthreads();
 
-  const uint32_t tile = pv.tile;
-  for (uint32_t c0 = 0; c0 < ntiles; c0 += kMergeThreads) {
-    // run of this partition in tile c0 + tid
-    uint32_t len = 0, lo = 0;
-    if (c0 + tid < ntiles) {
-      const uint32_t* offs = pv.runs + (uint64_t)(c0 + tid) * (P + 1) + p;
-      lo = offs[0];
-      len = offs[1] - lo;
-    }
-    __syncthreads();  // previous chunk done with s_start / s_lo
-    s_start[tid] = len;
-    s_lo[tid] = lo;
-    const uint32_t total = block_exclusive_scan<kMergeThreads>(s_start, kMergeThreads, s_wave);
-    if (tid == 0) s_start[kMergeThreads] = total;
-    __syncthreads();
-
-    for (uint32_t e0 = tid * kMergeBatch; e0 < total; e0 += kMergeThreads * kMergeBatch) {
-      // run holding e0: the last run whose start is <= e0 (empty runs share
-      // their start with the next run, so the last one is the non-empty one)
-      uint32_t a = 0, b = kMergeThreads - 1;
-      while (a < b) {
-        const uint32_t m = (a + b + 1) >> 1;
-        if (s_start[m] <= e0) a = m; else b = m - 1;
-      }
-      unsigned long long ek[kMergeBatch];
-      float er[kMergeBatch], eg[kMergeBatch], eb[kMergeBatch];
-      bool ev[kMergeBatch];
+  for (uint32_t g0 = w_lo; g0 < w_hi; g0 += 64 * kRunGroups) {
+    if (g0 != w_lo) load_runs(g0);
 #pragma unroll
-      for (uint32_t q = 0; q < kMergeBatch; ++q) {
-        const uint32_t e = e0 + q;
-        ev[q] = e < total;
-        if (!ev[q]) continue;
-        while (s_start[a + 1] <= e) ++a;
-        const uint64_t at = (uint64_t)(c0 + a) * tile + s_lo[a] + (e - s_start[a]);
-        ek[q] = pv.stage_key[at];
-        er[q] = pv.stage_rgb[3 * at];
-        eg[q] = pv.stage_rgb[3 * at + 1];
-        eb[q] = pv.stage_rgb[3 * at + 2];
-      }
+    for (uint32_t g = 0; g < kRunGroups; ++g) {
+      const uint32_t len = r_len[g] - r_lo[g];
+      uint32_t inc = len;
 #pragma unroll
-      for (uint32_t q = 0; q < kMergeBatch; ++q) {
-        if (!ev[q]) continue;
-        const unsigned long long key = ek[q];
-        const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
-        uint32_t slot = ~0u;
-        uint32_t i = 0;
-        for (; i < tv.max_probe; ++i) {
-          const uint32_t s = (start + i) & (B - 1);
-          unsigned long long cur = s_key[s];
-          if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
-          if (cur == kEmpty || cur == key) {
-            slot = s;
-            break;
+      for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += v;
+      }
+      const uint32_t excl = inc - len;
+      const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+      const uint64_t tbase = (uint64_t)(g0 + g * 64) * tile;
+      for (uint32_t e0 = 0; e0 < total; e0 += 64 * kEntryBatch) {
+        unsigned long long ek[kEntryBatch];
+        float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch];
+        bool ev[kEntryBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) {
+          const uint32_t e = e0 + q * 64 + lane;
+          const uint32_t a = wave_upper_bound(excl, e);
+          const uint32_t lo_a = (uint32_t)__shfl((int)r_lo[g], (int)a);
+          const uint32_t ex_a = (uint32_t)__shfl((int)excl, (int)a);
+          ev[q] = e < total;
+          if (!ev[q]) continue;
+          const uint64_t at = tbase + (uint64_t)a * tile + lo_a + (e - ex_a);
+          ek[q] = pv.stage_key[at];
+          er[q] = pv.stage_rgb[3 * at];
+          eg[q] = pv.stage_rgb[3 * at + 1];
+          eb[q] = pv.stage_rgb[3 * at + 2];
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) {
+          if (!ev[q]) continue;
+          const unsigned long long key = ek[q];
+          const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
+          uint32_t slot = ~0u;
+          uint32_t i = 0;
+          for (; i < tv.max_probe; ++i) {
+            const uint32_t s = (start + i) & (B - 1);
+            unsigned long long cur = s_key[s];
+            if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
+            if (cur == kEmpty || cur == key) {
+              slot = s;
+              break;
+            }
           }
+          if (slot == ~0u) {
+            atomicAdd(&s_dropped, 1u);
+            continue;
+          }
+          if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
+          atomicAdd(&s_cnt[slot], 1u);
+          atomicAdd(&s_sum0[slot], er[q]);
+          atomicAdd(&s_sum1[slot], eg[q]);
+          atomicAdd(&s_sum2[slot], eb[q]);
         }
-        if (slot == ~0u) {
-          atomicAdd(&s_dropped, 1u);
-          continue;
-        }
-        if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
-        atomicAdd(&s_cnt[slot], 1u);
-        atomicAdd(&s_sum0[slot], er[q]);
-        atomicAdd(&s_sum1[slot], eg[q]);
-        atomicAdd(&s_sum2[slot], eb[q]);
       }
     }
   }
   __syncthreads();
 
-  // write the partition back
+  // write the partition back; the old slots of a group are loaded together
+  // so the group costs one memory round trip
   bool sat = false;
   uint32_t touched = 0;
-  for (uint32_t s = tid; s < B; s += kMergeThreads) {
-    const uint32_t c = s_cnt[s];
-    if (c == 0) continue;
-    const uint64_t g = base + s;
-    Slot* d = &tv.slots[g];
-    const unsigned long long k = s_key[s];
-    if (kFused) {
-      const Slot old = *d;
-      const float alpha = blend_alpha(bp, c, old.c_old);
-      const float inv = 1.0f / (float)c;
-      float L[3];
-      load_state(old, bp.dtype, L[0], L[1], L[2]);
-      const float sums[3] = {s_sum0[s], s_sum1[s], s_sum2[s]};
-      float out[3];
-      for (int ch = 0; ch < 3; ++ch) {
-        const float m = sums[ch] * inv;
-        out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
-      }
-      uint32_t enc[4];
-      encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
-      Slot nw;
-      nw.key = k;
-      nw.c_old = old.c_old + c;
-      nw.pad = 0;
-      nw.L[0] = enc[0];
-      nw.L[1] = enc[1];
-      nw.L[2] = enc[2];
-      nw.L[3] = enc[3];
-      *d = nw;
-      if (old.key != k) tv.keys[g] = k;
-      ++touched;
-    } else {
-      Acc a = tv.acc[g];
-      a.n += c;
-      a.s[0] += s_sum0[s];
-      a.s[1] += s_sum1[s];
-      a.s[2] += s_sum2[s];
-      tv.acc[g] = a;
-      if (d->key != k) {
-        d->key = k;
-        tv.keys[g] = k;
+  constexpr uint32_t kWb = 4;
+  for (uint32_t s0 = 0; s0 < B; s0 += kWb * kMergeThreads) {
+    uint32_t cnt[kWb];
+    Slot old[kWb];
+    Acc acc_old[kWb];
+#pragma unroll
+    for (uint32_t j = 0; j < kWb; ++j) {
+      const uint32_t s = s0 + j * kMergeThreads + tid;
+      cnt[j] = s < B ? s_cnt[s] : 0u;
+      if (cnt[j] == 0) continue;
+      old[j] = tv.slots[base + s];
+      if (!kFused) acc_old[j] = tv.acc[base + s];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kWb; ++j) {
+      if (cnt[j] == 0) continue;
+      const uint32_t s = s0 + j * kMergeThreads + tid;
+      const uint64_t g = base + s;
+      const uint32_t c = cnt[j];
+      const unsigned long long k = s_key[s];
+      if (kFused) {
+        const float alpha = blend_alpha(bp, c, old[j].c_old);
+        const float inv = 1.0f / (float)c;
+        float L[3];
+        load_state(old[j], bp.dtype, L[0], L[1], L[2]);
+        const float sums[3] = {s_sum0[s], s_sum1[s], s_sum2[s]};
+        float out[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          const float m = sums[ch] * inv;
+          out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
+        }
+        uint32_t enc[4];
+        encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
+        Slot nw;
+        nw.key = k;
+        nw.c_old = old[j].c_old + c;
+        nw.pad = 0;
+        nw.L[0] = enc[0];
+        nw.L[1] = enc[1];
+        nw.L[2] = enc[2];
+        nw.L[3] = enc[3];
+        tv.slots[g] = nw;
+        if (old[j].key != k) tv.keys[g] = k;
+        ++touched;
+      } else {
+        Acc a = acc_old[j];
+        a.n += c;
+        a.s[0] += s_sum0[s];
+        a.s[1] += s_sum1[s];
+        a.s[2] += s_sum2[s];
+        tv.acc[g] = a;
+        if (old[j].key != k) {
+          tv.slots[g].key = k;
+          tv.keys[g] = k;
+        }
       }
     }
   }
@@ -329,7 +391,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
     if (s_dropped) atomicAdd(&tv.stats->dropped, (unsigned long long)s_dropped);
     if (kFused) {
       if (s_sat) atomicAdd(&tv.stats->saturated, (unsigned long long)s_sat);
-      BlockTouch* bt = &tv.touch[blockIdx.x];
+      BlockTouch* bt = &tv.touch[blk];
       bt->last = s_touched;
       bt->total += s_touched;
     }
@@ -338,33 +400,30 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView 
     atomicAdd(&tv.stats->probe_hist[tid], (unsigned long long)s_hist[tid]);
 }
 
+template <bool kFused>
+__global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles,
+                                                         BlendParams bp) {
+  merge_body<kFused>(tv, pv, ntiles, bp, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ cached-key lookup
+__device__ __forceinline__ void query_cached_one(const unsigned long long* rkeys, uint64_t n,
+                                                 const TableView& tv, int32_t dtype, float* out,
+                                                 uint8_t* found, uint64_t i) {
+  const unsigned long long key = rkeys[i];
+  float rgb[3];
+  const uint8_t hit = lookup_key(tv, dtype, key, rgb);
+  out[i] = rgb[0];
+  out[n + i] = rgb[1];
+  out[2 * n + i] = rgb[2];
+  if (found) found[i] = hit;
+}
+
 __global__ void __launch_bounds__(256) k_query_cached(const unsigned long long* rkeys, uint64_t n,
                                                       TableView tv, int32_t dtype, float* out,
                                                       uint8_t* found) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const unsigned long long key = rkeys[i];
-  float r = 0.0f, g = 0.0f, b = 0.0f;
-  uint8_t hit = 0;
-  if (key != kEmpty) {
-    const ProbeSeq ps = probe_seq(key, tv.log2_slots, tv.part_log2);
-    for (uint32_t j = 0; j < tv.max_probe; ++j) {
-      const Slot sl = tv.slots[ps.at(j)];
-      if (sl.key == key) {
-        if (sl.c_old > 0) {
-          load_state(sl, dtype, r, g, b);
-          hit = 1;
-        }
-        break;
-      }
-      if (sl.key == kEmpty) break;
-    }
-  }
-  out[i] = r;
-  out[n + i] = g;
-  out[2 * n + i] = b;
-  if (found) found[i] = hit;
+  if (i < n) query_cached_one(rkeys, n, tv, dtype, out, found, i);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -375,23 +434,14 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
 
 static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 12); }
 
-static hipError_t kernel_attrs() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  const int lim_m = (int)merge_lds(kMaxPartLog2);
-  const void* fns[] = {reinterpret_cast<const void*>(&k_merge<true>),
-                       reinterpret_cast<const void*>(&k_merge<false>),
-                       reinterpret_cast<const void*>(&k_bin<8>),
-                       reinterpret_cast<const void*>(&k_bin<12>),
-                       reinterpret_cast<const void*>(&k_bin<16>)};
-  const int lims[] = {lim_m, lim_m, (int)bin_lds(kTouchEntries, 8), (int)bin_lds(kTouchEntries, 12),
-                      (int)bin_lds(kTouchEntries, 16)};
-  for (int i = 0; i < 5; ++i) {
-    hipError_t a = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i]);
-    if (a != hipSuccess) return a;
-  }
-  done = true;
-  return hipSuccess;
+// Raise a kernel's dynamic-LDS limit only as far as the launch needs (and
+// only when it exceeds the default 64 KiB): the limit is per function and is
+// remembered, so it is set once per distinct requirement.
+static hipError_t lds_limit(const void* fn, size_t bytes, int* current) {
+  if (bytes <= 65536 || (int)bytes <= *current) return hipSuccess;
+  hipError_t a = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (a == hipSuccess) *current = (int)bytes;
+  return a;
 }
 
 static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
@@ -403,12 +453,15 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
                       const PartView& pv, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
-  hipError_t e = kernel_attrs();
-  if (e != hipSuccess) return e;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t per = pv.tile / kBinThreads;
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = bin_lds(P, per);
+  static int lim8 = 0, lim12 = 0, lim16 = 0;
+  hipError_t e = per == 8    ? lds_limit(reinterpret_cast<const void*>(&k_bin<8>), shm, &lim8)
+                 : per == 12 ? lds_limit(reinterpret_cast<const void*>(&k_bin<12>), shm, &lim12)
+                             : lds_limit(reinterpret_cast<const void*>(&k_bin<16>), shm, &lim16);
+  if (e != hipSuccess) return e;
   if (per == 8)
     k_bin<8><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
   else if (per == 12)
@@ -422,11 +475,13 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
                         hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
-  hipError_t e = kernel_attrs();
-  if (e != hipSuccess) return e;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = merge_lds(tv.part_log2);
+  static int lim_f = 0, lim_p = 0;
+  hipError_t e = fuse ? lds_limit(reinterpret_cast<const void*>(&k_merge<true>), shm, &lim_f)
+                      : lds_limit(reinterpret_cast<const void*>(&k_merge<false>), shm, &lim_p);
+  if (e != hipSuccess) return e;
   if (fuse)
     k_merge<true><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse);
   else
@@ -438,6 +493,90 @@ hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, cons
                                int32_t dtype, float* out, uint8_t* found, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_query_cached<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rkeys, n, tv, dtype, out, found);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched sessions
+// One launch per pass covers every session: a block finds its session by
+// its index among the sessions' block ranges (few sessions: a short scan of
+// uniform values) and runs the single-table body with the session's views.
+__device__ __forceinline__ uint32_t find_session(const BatchSession* ss, uint32_t k, uint32_t b,
+                                                 int which) {
+  uint32_t s = 0;
+  while (s + 1 < k) {
+    const BatchSession& nx = ss[s + 1];
+    const uint32_t begin = which == 0 ? nx.tile_begin : (which == 1 ? nx.part_begin : nx.qblk_begin);
+    if (begin > b) break;
+    ++s;
+  }
+  return s;
+}
+
+template <uint32_t kPer>
+__global__ void __launch_bounds__(kBinThreads) k_bin_batch(const BatchSession* ss, uint32_t k) {
+  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 0)];
+  const uint32_t local = blockIdx.x - S.tile_begin;
+  if (local >= S.ntiles) return;
+  bin_body<kPer>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+}
+
+__global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, uint32_t k) {
+  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 1)];
+  const uint32_t local = blockIdx.x - S.part_begin;
+  if (local >= S.nparts) return;
+  merge_body<true>(S.tv, S.pv, S.ntiles, S.bp, local);
+}
+
+__global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession* ss, uint32_t k) {
+  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 2)];
+  const uint64_t i = (uint64_t)(blockIdx.x - S.qblk_begin) * kQueryBlock + threadIdx.x;
+  if (i >= S.nq) return;
+  if (S.cached) {
+    query_cached_one(S.pv.rkeys, S.nq, S.tv, S.bp.dtype, S.out, S.found, i);
+    return;
+  }
+  float rgb[3];
+  const uint8_t hit = lookup_key(S.tv, S.bp.dtype, query_key(S.kp, S.q, i), rgb);
+  S.out[i] = rgb[0];
+  S.out[S.nq + i] = rgb[1];
+  S.out[2 * S.nq + i] = rgb[2];
+  if (S.found) S.found[i] = hit;
+}
+
+hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  uint32_t tiles = 0, parts = 0, qblks = 0;
+  size_t lds_b = 0, lds_m = 0;
+  const uint32_t per = h_ss[0].pv.tile / kBinThreads;
+  for (uint32_t i = 0; i < k; ++i) {
+    const BatchSession& S = h_ss[i];
+    if (S.n == 0 || !partition_ok(S.tv, S.pv, S.n) || S.pv.tile != h_ss[0].pv.tile ||
+        S.tile_begin != tiles || S.part_begin != parts || S.qblk_begin != qblks || (S.part_begin & 7u))
+      return hipErrorInvalidValue;
+    const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
+    const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv.part_log2);
+    lds_b = lb > lds_b ? lb : lds_b;
+    lds_m = lm > lds_m ? lm : lds_m;
+    tiles += S.ntiles;
+    parts += (S.nparts + 7u) & ~7u;
+    qblks += S.nqblk;
+  }
+  static int lim8 = 0, lim12 = 0, lim16 = 0, lim_m = 0;
+  hipError_t e = per == 8    ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<8>), lds_b, &lim8)
+                 : per == 12 ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<12>), lds_b, &lim12)
+                             : lds_limit(reinterpret_cast<const void*>(&k_bin_batch<16>), lds_b, &lim16);
+  if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
+  if (e != hipSuccess) return e;
+  if (per == 8)
+    k_bin_batch<8><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
+  else if (per == 12)
+    k_bin_batch<12><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
+  else
+    k_bin_batch<16><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_merge_batch<<<parts, kMergeThreads, lds_m, s>>>(d_ss, k);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (qblks) k_query_batch<<<qblks, kQueryBlock, 0, s>>>(d_ss, k);
   return hipGetLastError();
 }
 

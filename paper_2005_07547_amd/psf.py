@@ -88,7 +88,9 @@ EXPORTS = [
     ("psf_compute_keys", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp, _vp]),
     ("psf_get_stats", ctypes.c_int, [_vp, _P(psf_stats), _vp]),
     ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
-    ("psf_iterate_batch", ctypes.c_int, [_P(psf_session), _u32, _vp]),
+    ("psf_batch_create", ctypes.c_int, [_u32, _P(_vp)]),
+    ("psf_batch_destroy", ctypes.c_int, [_vp]),
+    ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
     ("psf_kernel_times", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     ("psf_kernel_name", ctypes.c_char_p, [_u32]),
     ("psf_last_error", ctypes.c_char_p, []),
@@ -288,21 +290,51 @@ class Table:
                 "L": rgb[:, :c][:, order]}
 
 
-def iterate_batch(tables, recs, queries, outs, founds):
-    """One batched iteration over several tables (psf_iterate_batch)."""
-    lib = load()
-    k = len(tables)
-    arr = (psf_session * k)()
-    for i in range(k):
-        s = arr[i]
-        s.table = tables[i].handle
-        s.rec = make_records(recs[i])
-        s.n = int(recs[i]["px"].numel())
-        s.q = make_queries(queries[i])
-        s.nq = int(queries[i]["px"].numel())
-        s.d_out_rgb = _ptr(outs[i])
-        s.d_out_found = _ptr(founds[i]) if founds[i] is not None else None
-    _check(lib.psf_iterate_batch(arr, k, current_stream()))
+class Batch:
+    """A batch context (psf_batch) for batched iterations over several tables."""
+
+    def __init__(self, max_sessions: int = 64):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.psf_batch_create(int(max_sessions), ctypes.byref(h)))
+        self.handle = h
+        self.max_sessions = int(max_sessions)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self._lib.psf_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, tables, recs, queries=None, outs=None, founds=None):
+        """One batched iteration; queries default to the records.  Returns
+        the (out, found) pairs."""
+        import torch
+        k = len(tables)
+        queries = recs if queries is None else queries
+        if outs is None:
+            outs = [torch.empty((3, int(q["px"].numel())), dtype=torch.float32, device="cuda")
+                    for q in queries]
+        if founds is None:
+            founds = [torch.empty(int(q["px"].numel()), dtype=torch.uint8, device="cuda")
+                      for q in queries]
+        arr = (psf_session * k)()
+        for i in range(k):
+            s = arr[i]
+            s.table = tables[i].handle
+            s.rec = make_records(recs[i])
+            s.n = int(recs[i]["px"].numel())
+            s.q = make_queries(queries[i])
+            s.nq = int(queries[i]["px"].numel())
+            s.d_out_rgb = _ptr(outs[i])
+            s.d_out_found = _ptr(founds[i]) if founds[i] is not None else None
+        _check(self._lib.psf_iterate_batch(self.handle, arr, k, current_stream()))
+        return list(zip(outs, founds))
 
 
 def version() -> str:

@@ -73,7 +73,7 @@ def precision():
            "field_scale": 4.0, "amp": (1.0, 0.8, 0.6), "glossy_lobe": 1}
     return {"name": "precision-1920x1080-5v", "scene": dict(kind=Scene.RANDOM, seed=3, glossy_frac=0.5),
             "gen": gen, "diffuse_only": False, "iterations": 64,
-            "table": _table(24, cam, 60.0, 1080, 4.0, -5)}
+            "table": _table(24, cam, 60.0, 1080, 8.0 * math.sqrt(2.0), -5)}
 
 
 BATCH_RES = ((256, 256), (512, 384), (640, 480), (1280, 720), (1920, 1080))
@@ -89,8 +89,8 @@ def batched_sessions(n_sessions=16, seed=4):
         r = philox4x32_10((i, 0, 0, 0), (seed, 0x0b47c4ed))
         spp = 1 + int(r[0] % 4)
         verts = 3 + int(r[1] % 3)
-        n = w * h * spp * verts
-        log2 = int(min(23, max(18, math.ceil(math.log2(max(1, n))))))
+        # distinct cells grow with pixels x vertices, not with spp
+        log2 = int(min(23, max(18, math.ceil(math.log2(max(1, w * h * verts))))))
         cam = (0.0, 0.0, -10.0)
         gen = {"width": w, "height": h, "spp": spp, "verts": verts, "seed": 100 + i, "cam": cam,
                "look": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "field": 0, "noise": 1,
@@ -98,7 +98,7 @@ def batched_sessions(n_sessions=16, seed=4):
         out.append({"name": f"session{i}-{w}x{h}-{spp}spp-{verts}v",
                     "scene": dict(kind=Scene.RANDOM, seed=100 + i, glossy_frac=-1.0),
                     "gen": gen, "diffuse_only": False, "iterations": 32,
-                    "table": _table(log2, cam, 60.0, h, 4.0, -5)})
+                    "table": _table(log2, cam, 60.0, h, 8.0 * math.sqrt(2.0), -5)})
     return out
 
 

@@ -42,7 +42,9 @@ def test_host_side_validation_without_gpu():
     h = ctypes.c_void_p()
     assert lib.psf_create_table(None, None, 0, None, ctypes.byref(h)) == psf.PSF_INVALID_ARGUMENT
     assert lib.psf_destroy(None) == psf.PSF_OK
-    assert lib.psf_iterate_batch(None, 0, None) == psf.PSF_OK
+    assert lib.psf_iterate_batch(None, None, 0, None) == psf.PSF_OK
+    assert lib.psf_iterate_batch(None, None, 2, None) == psf.PSF_INVALID_ARGUMENT
+    assert lib.psf_batch_destroy(None) == psf.PSF_OK
     assert lib.psf_version().startswith(b"psf")
 
 

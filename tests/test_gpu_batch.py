@@ -1,0 +1,130 @@
+"""Batched form: every session's result is the same alone and in the mix,
+matches the oracle, survives fallback sessions and hipGraph replay."""
+import numpy as np
+import pytest
+
+from tests.helpers import compare_cells, rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+RTOL_F32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2005_07547_amd import psf
+    psf.load()
+    return torch, psf
+
+
+def _sessions(n_sessions=5, scale=8):
+    """Uneven sessions of the batched workload, resolution divided by scale."""
+    from synth import workloads as W
+    out = []
+    for wl in W.batched_sessions(n_sessions):
+        g = dict(wl["gen"])
+        g["width"] = max(16, g["width"] // scale)
+        g["height"] = max(16, g["height"] // scale)
+        wl = dict(wl, gen=g, table=dict(wl["table"], log2_slots=max(14, wl["table"]["log2_slots"] - 4)))
+        out.append((wl, W.make_scene(wl)))
+    return out
+
+
+def _frame(wl, sc, it):
+    return sc.generate(wl["gen"], it)
+
+
+def test_batch_equals_alone_and_oracle(env):
+    import oracle
+    torch, psf = env
+    ss = _sessions()
+    alone = [psf.Table(**wl["table"]) for wl, _ in ss]
+    mixed = [psf.Table(**wl["table"]) for wl, _ in ss]
+    orcs = [oracle.Oracle(**wl["table"]) for wl, _ in ss]
+    batch = psf.Batch(16)
+    for it in range(3):
+        recs = [_frame(wl, sc, it) for wl, sc in ss]
+        dev = [to_device(r) for r in recs]
+        res_alone = [t.iterate(d) for t, d in zip(alone, dev)]
+        res_mix = batch.iterate(mixed, dev)
+        for o, r in zip(orcs, recs):
+            o.insert(r)
+            o.update()
+    torch.cuda.synchronize()
+    for i, (wl, _) in enumerate(ss):
+        ea, em = alone[i].export(), mixed[i].export()
+        assert np.array_equal(ea["keys"], em["keys"]) and np.array_equal(ea["c_old"], em["c_old"])
+        assert rel_err(em["L"], ea["L"]).max() <= RTOL_F32
+        compare_cells(em, orcs[i].export(), RTOL_F32, wl["name"])
+        (oa, fa), (om, fm) = res_alone[i], res_mix[i]
+        assert np.array_equal(fa.cpu().numpy(), fm.cpu().numpy())
+        assert rel_err(om.cpu().numpy(), oa.cpu().numpy()).max() <= RTOL_F32
+        st = mixed[i].stats()
+        assert st["updates"] == 3 and st["dropped"] == 0
+
+
+def test_batch_with_fallback_sessions_and_separate_queries(env):
+    import oracle
+    torch, psf = env
+    ss = _sessions(4)
+    tables = []
+    for j, (wl, _) in enumerate(ss):
+        mode = psf.PSF_INSERT_DIRECT if j == 1 else psf.PSF_INSERT_AUTO
+        tables.append(psf.Table(**dict(wl["table"], insert_mode=mode)))
+    orcs = [oracle.Oracle(**wl["table"]) for wl, _ in ss]
+    batch = psf.Batch(8)
+    for it in range(2):
+        recs = [_frame(wl, sc, it) for wl, sc in ss]
+        qrys = [_frame(wl, sc, 100 + it) for wl, sc in ss]  # different vertices
+        res = batch.iterate(tables, [to_device(r) for r in recs], [to_device(q) for q in qrys])
+        for o, r in zip(orcs, recs):
+            o.insert(r)
+            o.update()
+    torch.cuda.synchronize()
+    for i in range(len(ss)):
+        compare_cells(tables[i].export(), orcs[i].export(), RTOL_F32, f"session {i}")
+        w_out, w_found = orcs[i].query(qrys[i])
+        out, found = res[i]
+        assert np.array_equal(found.cpu().numpy(), w_found)
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+
+
+def test_batch_graph_replay_matches_eager(env):
+    """Capture one batched iteration in a graph and replay it several times,
+    with eager work and synchronisation between replays; every replay must
+    match the same sequence run eagerly."""
+    torch, psf = env
+    ss = _sessions(4)
+    frames = [to_device(_frame(wl, sc, 0)) for wl, sc in ss]
+    eager = [psf.Table(**wl["table"]) for wl, _ in ss]
+    graphed = [psf.Table(**wl["table"]) for wl, _ in ss]
+    b_eager, b_graph = psf.Batch(8), psf.Batch(8)
+    outs = [torch.empty((3, int(f["px"].numel())), dtype=torch.float32, device="cuda") for f in frames]
+    founds = [torch.empty(int(f["px"].numel()), dtype=torch.uint8, device="cuda") for f in frames]
+    # warm up the graphed tables once eagerly (kernel attributes, lazy state)
+    b_graph.iterate(graphed, frames, outs=outs, founds=founds)
+    b_eager.iterate(eager, frames)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b_graph.iterate(graphed, frames, outs=outs, founds=founds)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        ref = b_eager.iterate(eager, frames)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        del junk
+        for i in range(len(ss)):
+            ea, eg = eager[i].export(), graphed[i].export()
+            assert np.array_equal(ea["keys"], eg["keys"]), (rep, i)
+            assert np.array_equal(ea["c_old"], eg["c_old"]), (rep, i)
+            assert rel_err(eg["L"], ea["L"]).max() <= RTOL_F32
+            assert np.array_equal(ref[i][1].cpu().numpy(), founds[i].cpu().numpy())
+            assert rel_err(outs[i].cpu().numpy(), ref[i][0].cpu().numpy()).max() <= RTOL_F32
