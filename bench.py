@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -43,6 +44,26 @@ def algorithmic_bytes(n, c):
     }
 
 
+KERNEL_SYMBOL = {"bin": "k_bin", "merge_blend": "k_merge", "query": "k_query_cached",
+                 "merge": "k_merge", "update": "k_update", "insert_direct": "k_insert_direct"}
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (profiles/traffic_<workload>.json), or None when there is none or
+    the kernel sources changed since it was taken."""
+    from paper_2005_07547_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("digest") != profiling.source_digest():
+        return None
+    k = rec["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
+    return None if k is None else int(k["bytes"])
+
+
 def cpu_baseline(wl, rec, budget_s):
     """The oracle as it stands, single-threaded, on whole iterations of the
     same records until the time budget is used (at least one iteration)."""
@@ -66,6 +87,127 @@ def cpu_baseline(wl, rec, budget_s):
                       f"{wl['name']} workload, single thread, {el:.1f} s"}
 
 
+def _dev(rec, torch):
+    return {k: (None if v is None else torch.from_numpy(v).cuda()) for k, v in rec.items()}
+
+
+def form_precision(torch, psf, W, iters=12):
+    """Precision workload (1920x1080, 5 vertices, HDR): records/s of the fused
+    iteration for FP32, FP16 and BF16 approximant storage."""
+    import numpy as np
+    wl = W.precision()
+    sc = W.make_scene(wl)
+    n = W.records_per_iteration(wl)
+    frames = [_dev(sc.generate(wl["gen"], i), torch) for i in range(2)]
+    out = {}
+    for name in ("f32", "f16", "bf16"):
+        t = psf.Table(**dict(wl["table"], max_batch=n,
+                             state_dtype={"f32": 0, "f16": 1, "bf16": 2}[name]))
+        o = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        f = torch.empty(n, dtype=torch.uint8, device="cuda")
+        for i in range(2):
+            t.iterate(frames[i % 2], out=o, found=f)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(iters)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(iters):
+            ev[k][0].record()
+            t.iterate(frames[k % 2], out=o, found=f)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        st = t.stats()
+        out[name] = {"records_per_s": round(n * iters / el, 1), "ms_per_iter": round(el / iters * 1e3, 4),
+                     "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
+                     "saturated": st["saturated"], "dropped": st["dropped"]}
+        t.close()
+    return {"workload": wl["name"], "records_per_iteration": n, "by_state": out,
+            "note": "error vs the binary64 oracle is asserted in tests/test_gpu_precision.py"}
+
+
+def form_batched(torch, psf, W, iters=8, sessions=16):
+    """16 uneven sessions: one batched iteration per step versus the same
+    sessions iterated one after another (plain per-session path)."""
+    import numpy as np
+    wls = W.batched_sessions(sessions)
+    frames, ns = [], []
+    for wl in wls:
+        sc = W.make_scene(wl)
+        frames.append([_dev(sc.generate(wl["gen"], i), torch) for i in range(2)])
+        ns.append(W.records_per_iteration(wl))
+    total = sum(ns)
+    res = {}
+    for mode in ("plain_per_session", "batched"):
+        tabs = [psf.Table(**dict(wl["table"], max_batch=n)) for wl, n in zip(wls, ns)]
+        outs = [torch.empty((3, n), dtype=torch.float32, device="cuda") for n in ns]
+        fnds = [torch.empty(n, dtype=torch.uint8, device="cuda") for n in ns]
+        batch = psf.Batch(len(wls))
+
+        def step(k):
+            fr = [f[k % 2] for f in frames]
+            if mode == "batched":
+                batch.iterate(tabs, fr, outs=outs, founds=fnds)
+            else:
+                for t, r, o, f in zip(tabs, fr, outs, fnds):
+                    t.iterate(r, out=o, found=f)
+
+        for k in range(2):
+            step(k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(iters)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(iters):
+            ev[k][0].record()
+            step(k)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        res[mode] = {"records_per_s": round(total * iters / el, 1),
+                     "ms_per_iter": round(el / iters * 1e3, 4),
+                     "p50_iter_ms": round(float(np.percentile(ms, 50)), 4),
+                     "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
+                     "dropped": int(sum(t.stats()["dropped"] for t in tabs))}
+        for t in tabs:
+            t.close()
+        batch.close()
+        del tabs, outs, fnds
+    res["speedup_batched_over_plain"] = round(res["batched"]["records_per_s"] /
+                                              res["plain_per_session"]["records_per_s"], 3)
+    return {"sessions": len(wls), "records_per_iteration": total, **res}
+
+
+def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
+    """Poisson arrivals at 20/s, resolutions lognormal around 720p, 32-128
+    iterations each, 1 spp, 4 vertices; continuous batching under an HBM
+    budget.  Frames come from per-resolution-class pools in HBM."""
+    from paper_2005_07547_amd import serving
+    from synth import Scene
+    draws = serving.draw_requests(n_sessions, rate=rate, seed=5)
+    pools = {}
+    reqs = []
+    wl = W.plain()
+    for sid, arrival, cls, iters, seed in draws:
+        w, h = serving.RES_CLASSES[cls]
+        if cls not in pools:
+            gen = dict(wl["gen"], width=w, height=h, seed=700 + cls)
+            sc = Scene(Scene.RANDOM, seed=700 + cls, glossy_frac=-1.0 if cls % 2 else 0.5)
+            pools[cls] = [_dev(sc.generate(gen, f), torch) for f in range(2)]
+        log2 = int(min(24, max(16, math.ceil(math.log2(w * h * 4)))))
+        cfg = dict(wl["table"], log2_slots=log2,
+                   kappa=W.kappa_for(60.0, h, 8.0 * math.sqrt(2.0), -5))
+        reqs.append(serving.SessionRequest(sid=sid, arrival=arrival, iterations=iters, table_cfg=cfg,
+                                           frames=pools[cls], records=w * h * 4))
+    srv = serving.Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=64)
+    summ = srv.run(reqs, time_limit=240)
+    summ = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    summ.update({"arrival_rate_per_s": rate, "budget_gb": budget_gb})
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +221,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
+    ap.add_argument("--forms", default="precision,batched,serving",
+                    help="comma list of extra forms to measure (precision,batched,serving) or ''")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -169,8 +313,10 @@ def main():
                           "insert_direct": n * REC_BYTES + touched * CELL_INSERT}.get(dom, 0)
         ach = per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "algorithmic_bytes_per_launch": int(per_launch)}
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(wl["name"], dom),
+                    "algorithmic_bytes_per_launch": int(per_launch),
+                    "avg_launch_ms": round(kernels[dom]["avg_ms"], 5)}
     iter_gbs = ab["iteration"] / (elapsed / steps) / 1e9
     result = {
         "metric": "vertex records/s (insert+temporal update+query)",
@@ -198,9 +344,19 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    table.close()
+    del bufs, out, found
+    torch.cuda.empty_cache()
+    forms = {}
+    for name in [f for f in args.forms.split(",") if f]:
+        fn = {"precision": form_precision, "batched": form_batched, "serving": form_serving}[name]
+        print(f"# measuring form {name}", file=sys.stderr, flush=True)
+        forms[name] = fn(torch, psf, W)
+        torch.cuda.empty_cache()
+    if forms:
+        result["forms"] = forms
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, host[0], args.cpu_seconds)
-    table.close()
     print(json.dumps(result), flush=True)
 
 

@@ -97,33 +97,60 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   float rgb[kPer][3];
   uint32_t n_skip = 0, n_ovf = 0;
   const bool hr = rec.rough != nullptr;
+  // Every load is unconditional (indices past the end are clamped, absent
+  // arrays alias the positions) so that a batch of records is a single
+  // memory round trip; validity is applied afterwards.
+  const float* p_ox = hr ? rec.ox : rec.px;
+  const float* p_oy = hr ? rec.oy : rec.px;
+  const float* p_oz = hr ? rec.oz : rec.px;
+  const float* p_ro = hr ? rec.rough : rec.px;
+  constexpr uint32_t kLoad = 4;
 #pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j) {
-    pos[j] = ~0u;
-    const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
-    if (i >= n) continue;
-    const float ro = hr ? rec.rough[i] : 0.0f;
-    const bool gl = hr && ro < kp.rough_thr;
-    const float r = rec.r[i], g = rec.g[i], b = rec.b[i];
-    bool ovf = false;
-    uint64_t k;
-    bool ok = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
-                       gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro,
-                       k, ovf);
-    ok = ok && finite3(r, g, b);
-    if (pv.rkeys) pv.rkeys[i] = ok ? k : kEmpty;
-    if (!ok) {
-      ++n_skip;
-      continue;
+  for (uint32_t j0 = 0; j0 < kPer; j0 += kLoad) {
+    float f[kLoad][13];
+#pragma unroll
+    for (uint32_t q = 0; q < kLoad; ++q) {
+      const uint64_t i = t0 + (uint64_t)(j0 + q) * kBinThreads + tid;
+      const uint64_t ic = i < n ? i : n - 1;
+      f[q][0] = rec.px[ic];
+      f[q][1] = rec.py[ic];
+      f[q][2] = rec.pz[ic];
+      f[q][3] = rec.nx[ic];
+      f[q][4] = rec.ny[ic];
+      f[q][5] = rec.nz[ic];
+      f[q][6] = p_ox[ic];
+      f[q][7] = p_oy[ic];
+      f[q][8] = p_oz[ic];
+      f[q][9] = rec.r[ic];
+      f[q][10] = rec.g[ic];
+      f[q][11] = rec.b[ic];
+      f[q][12] = p_ro[ic];
     }
-    n_ovf += ovf ? 1u : 0u;
-    const uint32_t p = partition_of(fmix64(k), tv.log2_slots, tv.part_log2);
-    const uint32_t rank = atomicAdd(&s_hist[p], 1u);
-    key[j] = k;
-    pos[j] = (p << 16) | rank;
-    rgb[j][0] = r;
-    rgb[j][1] = g;
-    rgb[j][2] = b;
+#pragma unroll
+    for (uint32_t q = 0; q < kLoad; ++q) {
+      const uint32_t j = j0 + q;
+      pos[j] = ~0u;
+      const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
+      if (i >= n) continue;
+      bool ovf = false;
+      uint64_t k;
+      bool ok = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6], f[q][7],
+                         f[q][8], hr, f[q][12], k, ovf);
+      ok = ok && finite3(f[q][9], f[q][10], f[q][11]);
+      if (pv.rkeys) pv.rkeys[i] = ok ? k : kEmpty;
+      if (!ok) {
+        ++n_skip;
+        continue;
+      }
+      n_ovf += ovf ? 1u : 0u;
+      const uint32_t p = partition_of(fmix64(k), tv.log2_slots, tv.part_log2);
+      const uint32_t rank = atomicAdd(&s_hist[p], 1u);
+      key[j] = k;
+      pos[j] = (p << 16) | rank;
+      rgb[j][0] = f[q][9];
+      rgb[j][1] = f[q][10];
+      rgb[j][2] = f[q][11];
+    }
   }
   // rare-event counters: one atomic per wave when non-zero
   for (int off = 32; off > 0; off >>= 1) {
@@ -274,6 +301,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         unsigned long long ek[kEntryBatch];
         float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch];
         bool ev[kEntryBatch];
+        uint64_t at[kEntryBatch];
 #pragma unroll
         for (uint32_t q = 0; q < kEntryBatch; ++q) {
           const uint32_t e = e0 + q * 64 + lane;
@@ -281,12 +309,15 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           const uint32_t lo_a = (uint32_t)__shfl((int)r_lo[g], (int)a);
           const uint32_t ex_a = (uint32_t)__shfl((int)excl, (int)a);
           ev[q] = e < total;
-          if (!ev[q]) continue;
-          const uint64_t at = tbase + (uint64_t)a * tile + lo_a + (e - ex_a);
-          ek[q] = pv.stage_key[at];
-          er[q] = pv.stage_rgb[3 * at];
-          eg[q] = pv.stage_rgb[3 * at + 1];
-          eb[q] = pv.stage_rgb[3 * at + 2];
+          // lanes past the end read entry 0 of the tile (one shared line)
+          at[q] = tbase + (ev[q] ? (uint64_t)a * tile + lo_a + (e - ex_a) : 0ull);
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) {
+          ek[q] = pv.stage_key[at[q]];
+          er[q] = pv.stage_rgb[3 * at[q]];
+          eg[q] = pv.stage_rgb[3 * at[q] + 1];
+          eb[q] = pv.stage_rgb[3 * at[q] + 2];
         }
 #pragma unroll
         for (uint32_t q = 0; q < kEntryBatch; ++q) {
@@ -332,9 +363,14 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     for (uint32_t j = 0; j < kWb; ++j) {
       const uint32_t s = s0 + j * kMergeThreads + tid;
       cnt[j] = s < B ? s_cnt[s] : 0u;
-      if (cnt[j] == 0) continue;
-      old[j] = tv.slots[base + s];
-      if (!kFused) acc_old[j] = tv.acc[base + s];
+    }
+    // untouched slots all read the partition's first slot (one shared line)
+    // so the group's loads carry no branches and overlap
+#pragma unroll
+    for (uint32_t j = 0; j < kWb; ++j) {
+      const uint64_t src = base + (cnt[j] ? s0 + j * kMergeThreads + tid : 0u);
+      old[j] = tv.slots[src];
+      if (!kFused) acc_old[j] = tv.acc[src];
     }
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
