@@ -208,6 +208,36 @@ def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     return summ
 
 
+def graph_replay(torch, psf, wl, bufs, out, found, steps, n):
+    """The same iterations replayed from HIP graphs (one graph per input
+    buffer, captured from psf_iterate on a fresh table after an eager warm-up):
+    launch overhead removed."""
+    t = psf.Table(**dict(wl["table"], max_batch=max(n, 1)))
+    for b in bufs[:2]:
+        t.iterate(b, out=out, found=found)
+    torch.cuda.synchronize()
+    graphs = []
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for b in bufs:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                t.iterate(b, out=out, found=found)
+            graphs.append(g)
+    torch.cuda.current_stream().wait_stream(s)
+    for k in range(2):
+        graphs[k % len(graphs)].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        graphs[k % len(graphs)].replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t.close()
+    return {"value": round(n * steps / el, 1), "ms_per_step": round(el / steps * 1e3, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +251,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
     ap.add_argument("--forms", default="precision,batched,serving",
                     help="comma list of extra forms to measure (precision,batched,serving) or ''")
     ap.add_argument("--copy-calib", action="store_true",
@@ -345,6 +376,8 @@ def main():
         "roofline": roofline,
     }
     table.close()
+    if not args.no_graph and not args.split:
+        result["graph_replay"] = graph_replay(torch, psf, wl, bufs, out, found, args.steps, n)
     del bufs, out, found
     torch.cuda.empty_cache()
     forms = {}

@@ -48,12 +48,33 @@ def test_host_side_validation_without_gpu():
     assert lib.psf_version().startswith(b"psf")
 
 
-def test_struct_sizes_match_header():
-    # the binding's ctypes layouts against the C layouts compiled into a
-    # tiny probe program would need a compiler at test time; check the
-    # invariants the layout rests on instead
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures against the C layouts of include/psf.h,
+    compiled by the host C compiler."""
+    import shutil
+    import subprocess
     from paper_2005_07547_amd import psf
-    assert ctypes.sizeof(psf.psf_records) == 13 * 8
-    assert ctypes.sizeof(psf.psf_queries) == 10 * 8
-    assert ctypes.sizeof(psf.psf_config) == 88
-    assert ctypes.sizeof(psf.psf_stats) == 25 * 8
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = {"psf_config": psf.psf_config, "psf_records": psf.psf_records,
+               "psf_queries": psf.psf_queries, "psf_stats": psf.psf_stats,
+               "psf_session": psf.psf_session}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psf.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        k, v = line.rsplit(" ", 1)
+        got[k] = int(v)
+    for name, cls in structs.items():
+        assert got[f"{name} size"] == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[f"{name}.{fname}"] == getattr(cls, fname).offset, (name, fname)
