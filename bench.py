@@ -196,7 +196,7 @@ def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
             gen = dict(wl["gen"], width=w, height=h, seed=700 + cls)
             sc = Scene(Scene.RANDOM, seed=700 + cls, glossy_frac=-1.0 if cls % 2 else 0.5)
             pools[cls] = [_dev(sc.generate(gen, f), torch) for f in range(2)]
-        log2 = int(min(24, max(16, math.ceil(math.log2(w * h * 4)))))
+        log2 = int(min(25, max(16, math.ceil(math.log2(w * h * 4)) + 1)))
         cfg = dict(wl["table"], log2_slots=log2,
                    kappa=W.kappa_for(60.0, h, 8.0 * math.sqrt(2.0), -5))
         reqs.append(serving.SessionRequest(sid=sid, arrival=arrival, iterations=iters, table_cfg=cfg,

@@ -70,6 +70,7 @@ class Server:
         self.peak_active = 0
         self.ticks = 0
         self.records = 0
+        self.dropped = 0
         self._torch = torch
 
     def _admit(self, s: SessionRequest, now: float):
@@ -83,6 +84,7 @@ class Server:
     def _retire(self, s: SessionRequest, now: float):
         s.finished_at = now
         self.resident -= s.footprint
+        self.dropped += s.table.stats()["dropped"]
         if not self.keep_tables:
             s.table.close()
             s.table = None
@@ -161,6 +163,7 @@ class Server:
             "wall_s": wall, "records_per_s": self.records / wall if wall > 0 else math.nan,
             "p50_iter_ms": pct(50), "p99_iter_ms": pct(99),
             "peak_active": self.peak_active, "peak_resident_bytes": self.peak_resident,
+            "dropped": self.dropped,
             "mean_queue_s": sum(s.admitted_at - s.arrival for s in finished) / max(1, len(finished)),
         }
 

@@ -28,7 +28,10 @@ def _requests(serving, n=6, scale_classes=(0, 1, 1, 2, 0, 1), iters=(4, 6, 3, 5,
         gen = dict(wl["gen"], width=w, height=h, seed=900 + i)
         sc = Scene(Scene.RANDOM, seed=900 + i, glossy_frac=-1.0 if i % 2 else 0.5)
         frames = [to_device(sc.generate(gen, f)) for f in range(2)]
-        cfg = dict(wl["table"], log2_slots=16)
+        # cells sized for this resolution; four slots per record keeps every
+        # partition far from full over the session
+        cfg = dict(wl["table"], log2_slots=max(16, int(np.ceil(np.log2(w * h * 4))) + 2),
+                   kappa=W.kappa_for(60.0, h, 8.0 * np.sqrt(2.0), -5))
         reqs.append(serving.SessionRequest(sid=i, arrival=arrivals[i], iterations=iters[i],
                                            table_cfg=cfg, frames=frames, records=w * h * 4))
     return reqs
@@ -51,6 +54,7 @@ def test_results_same_alone_and_in_the_mix(env):
         assert np.array_equal(ea["c_old"], em["c_old"]), r.sid
         assert rel_err(em["L"], ea["L"]).max() <= RTOL_F32
         assert r.table.stats()["updates"] == r.iterations
+        assert r.table.stats()["dropped"] == 0
         assert len(r.latencies_ms) == r.iterations
 
 
