@@ -16,6 +16,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -60,8 +61,11 @@ def measured_traffic(workload: str, kernel: str):
         rec = json.load(f)
     if rec.get("digest") != profiling.source_digest():
         return None
-    k = rec["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
-    return None if k is None else int(k["bytes"])
+    sym = KERNEL_SYMBOL.get(kernel, kernel)
+    # rocprofv3 records demangled names ("void psf::k_merge<true>(...)")
+    pat = re.compile(r"(^|[\s:])" + re.escape(sym) + r"[<(]")
+    hits = [v for name, v in rec["kernels"].items() if pat.search(name)]
+    return int(hits[0]["bytes"]) if len(hits) == 1 else None
 
 
 def cpu_baseline(wl, rec, budget_s):
