@@ -224,7 +224,9 @@ __device__ __forceinline__ uint32_t wave_upper_bound(uint32_t excl, uint32_t e) 
 template <bool kFused>
 __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& pv, uint32_t ntiles,
                                            const BlendParams& bp, uint32_t blk) {
-  extern __shared__ unsigned long long s_dyn[];  // key[B] | cnt[B] | sum[3][B]
+  // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
+  // than f32 ones on gfx950 and exact enough to make the sum order immaterial)
+  extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
@@ -236,9 +238,9 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   const bool stats = (tv.flags & 1u) != 0;
   unsigned long long* s_key = s_dyn;
   uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_key + B);
-  float* s_sum0 = reinterpret_cast<float*>(s_cnt + B);
-  float* s_sum1 = s_sum0 + B;
-  float* s_sum2 = s_sum1 + B;
+  double* s_sum0 = reinterpret_cast<double*>(s_cnt + B);  // B >= 256: 8-byte aligned
+  double* s_sum1 = s_sum0 + B;
+  double* s_sum2 = s_sum1 + B;
   const uint32_t tile = pv.tile;
 
   // Each wave owns a contiguous slice of the tiles; it keeps up to
@@ -276,7 +278,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     if (s < B) {
       s_key[s] = kk[j];
       s_cnt[s] = 0;
-      s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0f;
+      s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0;
     }
   }
   if (tid == 0) s_dropped = s_touched = s_sat = 0;
@@ -341,9 +343,9 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           }
           if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
           atomicAdd(&s_cnt[slot], 1u);
-          atomicAdd(&s_sum0[slot], er[q]);
-          atomicAdd(&s_sum1[slot], eg[q]);
-          atomicAdd(&s_sum2[slot], eb[q]);
+          atomicAdd(&s_sum0[slot], (double)er[q]);
+          atomicAdd(&s_sum1[slot], (double)eg[q]);
+          atomicAdd(&s_sum2[slot], (double)eb[q]);
         }
       }
     }
@@ -381,13 +383,14 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       const unsigned long long k = s_key[s];
       if (kFused) {
         const float alpha = blend_alpha(bp, c, old[j].c_old);
-        const float inv = 1.0f / (float)c;
         float L[3];
         load_state(old[j], bp.dtype, L[0], L[1], L[2]);
-        const float sums[3] = {s_sum0[s], s_sum1[s], s_sum2[s]};
+        // the new sample mean, rounded once from binary64
+        const float means[3] = {(float)(s_sum0[s] / (double)c), (float)(s_sum1[s] / (double)c),
+                                (float)(s_sum2[s] / (double)c)};
         float out[3];
         for (int ch = 0; ch < 3; ++ch) {
-          const float m = sums[ch] * inv;
+          const float m = means[ch];
           out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
         }
         uint32_t enc[4];
@@ -406,9 +409,9 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       } else {
         Acc a = acc_old[j];
         a.n += c;
-        a.s[0] += s_sum0[s];
-        a.s[1] += s_sum1[s];
-        a.s[2] += s_sum2[s];
+        a.s[0] += (float)s_sum0[s];
+        a.s[1] += (float)s_sum1[s];
+        a.s[2] += (float)s_sum2[s];
         tv.acc[g] = a;
         if (old[j].key != k) {
           tv.slots[g].key = k;
@@ -468,7 +471,7 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
   return hist > stage ? hist : stage;
 }
 
-static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 12); }
+static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 24); }
 
 // Raise a kernel's dynamic-LDS limit only as far as the launch needs (and
 // only when it exceeds the default 64 KiB): the limit is per function and is
