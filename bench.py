@@ -45,7 +45,7 @@ def algorithmic_bytes(n, c):
     }
 
 
-KERNEL_SYMBOL = {"bin": "k_bin", "merge_blend": "k_merge", "query": "k_query_cached",
+KERNEL_SYMBOL = {"bin": "k_bin", "merge_blend": "k_merge", "query": "k_unstage",
                  "merge": "k_merge", "update": "k_update", "insert_direct": "k_insert_direct"}
 
 

@@ -81,8 +81,12 @@ enum {
 
 /* psf_config.flags */
 enum {
-  PSF_FLAG_PROBE_STATS = 1u, /* record a probe-length histogram */
-  PSF_FLAG_TIMING = 2u       /* bracket every kernel launch with HIP events */
+  PSF_FLAG_PROBE_STATS = 1u,   /* record a probe-length histogram */
+  PSF_FLAG_TIMING = 2u,        /* bracket every kernel launch with HIP events */
+  PSF_FLAG_TRANSPOSE_RUNS = 4u /* partitioned insert: always transpose the
+                                  per-tile run table before the merge pass
+                                  (by default only tables of 2^22 entries
+                                  or more are transposed) */
 };
 
 /* Kernel kinds reported by psf_kernel_times. */
@@ -95,7 +99,8 @@ enum {
   PSF_K_UPDATE = 5,
   PSF_K_QUERY = 6,
   PSF_K_BATCH = 7,
-  PSF_K_COUNT = 8
+  PSF_K_TRANSPOSE = 8,
+  PSF_K_COUNT = 9
 };
 
 /*
@@ -133,7 +138,8 @@ typedef struct psf_config {
   uint32_t part_log2;        /* partitioned insert: log2 slots per partition
                                 (0 = default 11, else 8..12) */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
-                                (0 = default 4M); larger inserts are split */
+                                (0 = default 4M, at most 2^31); larger
+                                inserts are split */
   uint32_t bin_per;          /* partitioned insert: records per thread of the
                                 binning pass (0 = default 8, else 8, 12, 16);
                                 a binning tile is 512 * bin_per records */
@@ -211,7 +217,9 @@ psf_status psf_query(psf_table* t, const psf_queries* q, uint64_t n, float* d_ou
 
 /* One whole iteration: insert rec, temporal update, then query q.  Same
  * result as the three calls in sequence; when the table has no pending
- * inserts the partitioned strategy fuses insert and blend in one pass. */
+ * inserts the partitioned strategy fuses insert and blend in one pass, and
+ * when q is rec itself (the same arrays, nq == n) that pass also hands every
+ * record its cell's new value, so the query costs no second lookup. */
 psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const psf_queries* q,
                        uint64_t nq, float* d_out_rgb, uint8_t* d_out_found, psf_stream stream);
 
@@ -242,7 +250,7 @@ psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint3
  * different from the first batchable session's) run through psf_iterate
  * first, on the same stream.  d_out_rgb (3*nq floats, SoA) and d_out_found
  * (nullable) as in psf_query; queries equal to the records (the same
- * arrays) reuse the keys computed while binning. */
+ * arrays) are answered by the merge pass, as in psf_iterate. */
 typedef struct psf_session {
   psf_table* table;
   psf_records rec;

@@ -142,16 +142,17 @@ bool validate(const psf_config* c, std::string* why) {
   if (c->state_dtype < 0 || c->state_dtype > 2) return bad("state_dtype must be F32, F16 or BF16");
   if (c->insert_mode < 0 || c->insert_mode > 2) return bad("insert_mode must be AUTO, DIRECT or PARTITIONED");
   if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
-  if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING)) return bad("unknown flags");
-  if (c->max_batch > (1ull << 32)) return bad("max_batch must be <= 2^32");
+  if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS))
+    return bad("unknown flags");
+  if (c->max_batch > (1ull << 31)) return bad("max_batch must be <= 2^31");
   if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
   if (c->reserved != 0) return bad("reserved must be 0");
   return true;
 }
 
 struct Layout {
-  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0,
-         rkeys = 0, total = 0;
+  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0, runs_t = 0,
+         perm = 0, total = 0;
   uint32_t part_log2 = 0;
   bool part = false;
   uint64_t cap = 0;
@@ -187,8 +188,10 @@ Layout layout_of(const psf_config& c) {
     off = align_up(off + L.cap * 12, 256);
     L.runs = off;
     off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
-    L.rkeys = off;
-    off = align_up(off + L.cap * 8, 256);
+    L.runs_t = off;  // rows padded to a multiple of 4 tiles (16-byte loads)
+    off = align_up(off + (P + 1) * (uint64_t)((L.tiles + 3) & ~3u) * 4, 256);
+    L.perm = off;
+    off = align_up(off + L.cap * 2, 256);
   }
   L.total = off;
   return L;
@@ -237,15 +240,27 @@ psf::RecPtrs offset_rec(const psf::RecPtrs& rp, uint64_t off) {
   return sub;
 }
 
+// Whether a partitioned launch of ntiles tiles transposes its run table.
+bool transpose_runs(const psf_table* t, uint32_t ntiles) {
+  return (t->cfg.flags & PSF_FLAG_TRANSPOSE_RUNS) ||
+         psf::transpose_pays(ntiles, 1u << (t->cfg.log2_slots - t->tv.part_log2));
+}
+
 psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream_t s) {
   hipError_t e;
   if (t->partitioned) {
     for (uint64_t off = 0; off < n; off += t->pv.capacity) {
       const uint64_t m = (n - off < t->pv.capacity) ? n - off : t->pv.capacity;
       const psf::RecPtrs sub = offset_rec(rp, off);
-      e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(sub, m, t->kp, t->tv, t->pv, s); });
+      psf::PartView pv = t->pv;
+      pv.perm = nullptr;
+      const uint32_t nt = (uint32_t)((m + pv.tile - 1) / pv.tile);
+      if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
+      e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(sub, m, t->kp, t->tv, pv, s); });
+      if (e == hipSuccess && pv.runs_t)
+        e = timed(t, PSF_K_TRANSPOSE, s, [&] { return psf::launch_transpose_runs(t->tv, pv, nt, s); });
       if (e == hipSuccess)
-        e = timed(t, PSF_K_MERGE, s, [&] { return psf::launch_merge(m, t->tv, t->pv, nullptr, s); });
+        e = timed(t, PSF_K_MERGE, s, [&] { return psf::launch_merge(m, t->tv, pv, nullptr, false, s); });
       if (e != hipSuccess) return hip_fail(e, "partitioned insert launch");
     }
   } else {
@@ -338,7 +353,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
     t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
     t->pv.stage_rgb = reinterpret_cast<float*>(b + L.stage_rgb);
     t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
-    t->pv.rkeys = reinterpret_cast<unsigned long long*>(b + L.rkeys);
+    t->pv.runs_t = reinterpret_cast<uint32_t*>(b + L.runs_t);
+    t->pv.perm = reinterpret_cast<uint16_t*>(b + L.perm);
     t->pv.tile = psf::bin_tile(cfg->bin_per ? cfg->bin_per : kDefaultBinPer);
     t->pv.max_tiles = L.tiles;
     t->pv.capacity = L.cap;
@@ -423,19 +439,25 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
   psf_status st = PSF_OK;
   if (n > 0 && t->partitioned && !t->pending && n <= t->pv.capacity) {
     const psf::RecPtrs rp = rec_ptrs(rec);
-    hipError_t e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(rp, n, t->kp, t->tv, t->pv, s); });
+    // when the queries are the records being inserted, the merge pass hands
+    // every staged entry its cell's new value and the unstage pass returns
+    // them in record order: no second lookup
+    const bool fq = nq == n && same_vertices(rec, q);
+    psf::PartView pv = t->pv;
+    if (!fq) pv.perm = nullptr;
+    const uint32_t nt = (uint32_t)((n + pv.tile - 1) / pv.tile);
+    if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
+    hipError_t e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(rp, n, t->kp, t->tv, pv, s); });
+    if (e == hipSuccess && pv.runs_t)
+      e = timed(t, PSF_K_TRANSPOSE, s, [&] { return psf::launch_transpose_runs(t->tv, pv, nt, s); });
     if (e == hipSuccess)
-      e = timed(t, PSF_K_MERGE_BLEND, s, [&] { return psf::launch_merge(n, t->tv, t->pv, &t->bp, s); });
+      e = timed(t, PSF_K_MERGE_BLEND, s, [&] { return psf::launch_merge(n, t->tv, pv, &t->bp, fq, s); });
     if (e != hipSuccess) return hip_fail(e, "fused insert launch");
     t->submitted += n;
     t->updates++;
     t->touch_entries = 1u << (t->cfg.log2_slots - t->tv.part_log2);
-    if (nq == n && same_vertices(rec, q)) {
-      // the queries are the records just binned: reuse their keys
-      e = timed(t, PSF_K_QUERY, s, [&] {
-        return psf::launch_query_cached(t->pv.rkeys, n, t->tv, t->cfg.state_dtype, d_out_rgb,
-                                        d_out_found, s);
-      });
+    if (fq) {
+      e = timed(t, PSF_K_QUERY, s, [&] { return psf::launch_unstage(n, t->tv, pv, d_out_rgb, d_out_found, s); });
       return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
     }
   } else {
@@ -650,7 +672,7 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
     if (e != hipSuccess) return hip_fail(e, "batch descriptor reuse");
     b->in_flight = false;
   }
-  uint32_t tiles = 0, parts = 0, qblks = 0;
+  uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   for (uint32_t j = 0; j < batch.size(); ++j) {
     const psf_session& ss = sessions[batch[j]];
     psf_table* t = ss.table;
@@ -666,15 +688,20 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
     if (ss.nq > 0) d.q = qry_ptrs(&ss.q);
     d.out = ss.d_out_rgb;
     d.found = ss.d_out_found;
-    d.cached = (ss.nq == ss.n && same_vertices(&ss.rec, &ss.q)) ? 1 : 0;
+    d.fused_query = (ss.nq == ss.n && same_vertices(&ss.rec, &ss.q)) ? 1 : 0;
+    if (!d.fused_query) d.pv.perm = nullptr;
     d.tile_begin = tiles;
     d.ntiles = (uint32_t)((ss.n + t->pv.tile - 1) / t->pv.tile);
     d.part_begin = parts;
     d.nparts = 1u << (t->cfg.log2_slots - t->tv.part_log2);
+    d.trans_begin = trans;
+    if (!transpose_runs(t, d.ntiles)) d.pv.runs_t = nullptr;
+    d.ntrans = d.pv.runs_t ? psf::transpose_blocks(d.ntiles, d.nparts) : 0u;
     d.qblk_begin = qblks;
-    d.nqblk = (uint32_t)((ss.nq + psf::kQueryBlock - 1) / psf::kQueryBlock);
+    d.nqblk = d.fused_query ? d.ntiles : (uint32_t)((ss.nq + psf::kQueryBlock - 1) / psf::kQueryBlock);
     tiles += d.ntiles;
     parts += (d.nparts + 7u) & ~7u;
+    trans += d.ntrans;
     qblks += d.nqblk;
   }
   const uint32_t m = (uint32_t)batch.size();
@@ -713,7 +740,7 @@ PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* to
 
 PSF_API const char* psf_kernel_name(uint32_t k) {
   static const char* names[PSF_K_COUNT] = {"keys", "insert_direct", "bin", "merge", "merge_blend",
-                                           "update", "query", "batch"};
+                                           "update", "query", "batch", "transpose"};
   return k < PSF_K_COUNT ? names[k] : "";
 }
 

@@ -22,7 +22,12 @@ struct PartView {
   unsigned long long* stage_key;  // staged sample keys, grouped per tile by partition
   float* stage_rgb;               // staged sample values (r, g, b triples), same order
   uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile
-  unsigned long long* rkeys;      // key of every record of the last binning, record order
+  uint32_t* runs_t;               // the same, transposed: [partition + 1][max_tiles]
+                                  // (null: not transposed for this launch)
+  // Staged position (in its tile) of every record of the binning, record
+  // order; kNoPos for a skipped record.  Written only when non-null (the
+  // fused query of an iteration whose queries are its records).
+  uint16_t* perm;
   uint32_t tile;                  // records per binning tile
   uint32_t max_tiles;             // tiles per launch
   uint64_t capacity;              // records per launch
@@ -42,14 +47,30 @@ hipError_t launch_count_occupied(const TableView& tv, uint64_t nslots, unsigned 
                                  hipStream_t s);
 // Partitioned insertion of n <= pv.capacity records: bin, then merge.
 // fuse != nullptr applies the temporal blend in the merge pass (the table
-// must hold no pending samples).
+// must hold no pending samples); with results set as well, the merge pass
+// also writes each staged entry's updated cell value over the entry (the
+// bin pass must have written pv.perm), and launch_unstage then gathers them
+// back into record order: the query of the records just inserted.
 hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
                       const PartView& pv, hipStream_t s);
 hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
-                        hipStream_t s);
-// Lookup of the records binned last, by their cached keys.
-hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, const TableView& tv,
-                               int32_t dtype, float* out, uint8_t* found, hipStream_t s);
+                        bool results, hipStream_t s);
+// runs -> runs_t for the first ntiles tiles (between bin and merge); a
+// no-op when runs_t is null (the merge pass then reads runs in place).  The
+// transpose pays once the table is large: from kTransposeMinWords entries.
+constexpr uint64_t kTransposeMinWords = 1ull << 22;
+bool transpose_pays(uint32_t ntiles, uint32_t nparts);
+hipError_t launch_transpose_runs(const TableView& tv, const PartView& pv, uint32_t ntiles, hipStream_t s);
+uint32_t transpose_blocks(uint32_t ntiles, uint32_t nparts);  // blocks of one transpose
+hipError_t launch_unstage(uint64_t n, const TableView& tv, const PartView& pv, float* out,
+                          uint8_t* found, hipStream_t s);
+constexpr uint16_t kNoPos = 0xffffu;  // perm of a record without a valid key
+// Result of a staged entry whose key has no blended cell: a NaN pattern in
+// the red channel (real values are finite).
+constexpr uint32_t kDroppedBits = 0xffffffffu;
+// Staged key of a record with a valid key but a rejected (non-finite)
+// sample: looked up, not inserted.  Valid keys never set bit 63.
+constexpr unsigned long long kLookupOnlyBit = 1ull << 63;
 bool bin_per_ok(uint32_t per);          // supported records per thread of the binning pass
 uint32_t bin_tile(uint32_t per);        // records per binning tile
 uint32_t update_grid(uint64_t nslots);  // blocks of the streaming update
@@ -67,8 +88,9 @@ struct BatchSession {
   uint8_t* found;
   uint32_t tile_begin, ntiles;  // binning blocks
   uint32_t part_begin, nparts;  // merge blocks (part_begin is a multiple of 8)
-  uint32_t qblk_begin, nqblk;   // query blocks
-  int32_t cached;               // queries are the binned records: use their keys
+  uint32_t trans_begin, ntrans;  // run-table transpose blocks
+  uint32_t qblk_begin, nqblk;   // query blocks (one per tile when fused)
+  int32_t fused_query;          // queries are the binned records: merge + unstage answer them
   int32_t pad;
 };
 

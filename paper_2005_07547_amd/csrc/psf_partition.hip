@@ -134,18 +134,17 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       if (i >= n) continue;
       bool ovf = false;
       uint64_t k;
-      bool ok = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6], f[q][7],
-                         f[q][8], hr, f[q][12], k, ovf);
-      ok = ok && finite3(f[q][9], f[q][10], f[q][11]);
-      if (pv.rkeys) pv.rkeys[i] = ok ? k : kEmpty;
-      if (!ok) {
-        ++n_skip;
-        continue;
-      }
-      n_ovf += ovf ? 1u : 0u;
+      const bool kv = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
+                               f[q][7], f[q][8], hr, f[q][12], k, ovf);
+      const bool sv = finite3(f[q][9], f[q][10], f[q][11]);
+      if (!(kv && sv)) ++n_skip;
+      // a record whose sample is rejected but whose key is valid is still a
+      // query vertex: with the fused query it is staged for lookup only
+      if (!kv || (!sv && !pv.perm)) continue;
+      n_ovf += (ovf && sv) ? 1u : 0u;
       const uint32_t p = partition_of(fmix64(k), tv.log2_slots, tv.part_log2);
       const uint32_t rank = atomicAdd(&s_hist[p], 1u);
-      key[j] = k;
+      key[j] = sv ? k : k | kLookupOnlyBit;
       pos[j] = (p << 16) | rank;
       rgb[j][0] = f[q][9];
       rgb[j][1] = f[q][10];
@@ -169,6 +168,13 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j)
     if (pos[j] != ~0u) pos[j] = s_hist[pos[j] >> 16] + (pos[j] & 0xffffu);
+  if (pv.perm) {
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
+      if (i < n) pv.perm[i] = pos[j] != ~0u ? (uint16_t)pos[j] : kNoPos;
+    }
+  }
   __syncthreads();  // the histogram is dead from here on; its LDS becomes staging
 
 #pragma unroll
@@ -195,6 +201,34 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, Ke
   bin_body<kPer>(rec, n, kp, tv, pv, blockIdx.x);
 }
 
+// ------------------------------------------------------------------ run table transpose
+// The merge block of partition p needs the offsets of p and p + 1 in every
+// tile: a column of the bin pass's [tile][P + 1] table.  A 64 x 64 LDS
+// transpose turns the columns into rows, so the merge reads them coalesced.
+constexpr uint32_t kTransposeDim = 64, kTransposeThreads = 256;
+
+__device__ __forceinline__ void transpose_body(const PartView& pv, uint32_t P, uint32_t ntiles, uint32_t bx,
+                                               uint32_t by) {
+  __shared__ uint32_t s_t[kTransposeDim][kTransposeDim + 1];
+  const uint32_t tid = threadIdx.x, c = tid % kTransposeDim, r0 = tid / kTransposeDim;
+  constexpr uint32_t kRowsPerPass = kTransposeThreads / kTransposeDim;
+  const uint32_t t0 = bx * kTransposeDim, p0 = by * kTransposeDim;
+  const uint32_t stride = (pv.max_tiles + 3u) & ~3u;
+  for (uint32_t r = r0; r < kTransposeDim; r += kRowsPerPass) {
+    const uint32_t t = t0 + r, p = p0 + c;
+    if (t < ntiles && p <= P) s_t[r][c] = pv.runs[(uint64_t)t * (P + 1) + p];
+  }
+  __syncthreads();
+  for (uint32_t r = r0; r < kTransposeDim; r += kRowsPerPass) {
+    const uint32_t p = p0 + r, t = t0 + c;
+    if (t < ntiles && p <= P) pv.runs_t[(uint64_t)p * stride + t] = s_t[c][r];
+  }
+}
+
+__global__ void __launch_bounds__(kTransposeThreads) k_transpose_runs(PartView pv, uint32_t P, uint32_t ntiles) {
+  transpose_body(pv, P, ntiles, blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------------------ merge
 // Blocks are dispatched to the 8 XCDs round-robin; give each XCD a
 // contiguous range of partitions so the offset rows they share stay in one
@@ -204,8 +238,12 @@ __device__ __forceinline__ uint32_t xcd_partition(uint32_t b, uint32_t P) {
   return (b & 7u) * (P >> 3) + (b >> 3);
 }
 
-constexpr uint32_t kRunGroups = 4;   // groups of 64 tile runs a wave keeps in registers
+constexpr uint32_t kRunsPerLane = 4;  // consecutive tile runs each lane keeps in registers
 constexpr uint32_t kEntryBatch = 4;  // entries per lane loaded before processing
+// Batches per wave whose (entry, slot) pairs stay in registers for the
+// fused query; a wave with more batches finds the later entries' slots again.
+constexpr uint32_t kKeepBatches = 2;
+constexpr uint32_t kLookupLater = 0xfffffffeu;  // kept slot of a lookup-only entry
 
 // Largest lane l with excl[l] <= e, where excl is a non-decreasing per-lane
 // value (all lanes of the wave must call this).
@@ -220,12 +258,16 @@ __device__ __forceinline__ uint32_t wave_upper_bound(uint32_t excl, uint32_t e) 
 }
 
 // One partition: blk is the block's index among the partition blocks of this
-// table (the XCD-aware order maps it to a partition).
+// table (the XCD-aware order maps it to a partition).  With results (fused
+// mode only), every staged entry of the partition is overwritten with the
+// value its cell holds after the blend (kDroppedBits in place of red when
+// its key found no slot).
 template <bool kFused>
 __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& pv, uint32_t ntiles,
-                                           const BlendParams& bp, uint32_t blk) {
+                                           const BlendParams& bp, uint32_t blk, bool results) {
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
-  // than f32 ones on gfx950 and exact enough to make the sum order immaterial)
+  // than f32 ones on gfx950 and exact enough to make the sum order
+  // immaterial).  After the blend the sums hold the cells' new values.
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
@@ -242,25 +284,105 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   double* s_sum1 = s_sum0 + B;
   double* s_sum2 = s_sum1 + B;
   const uint32_t tile = pv.tile;
+  if (!kFused) results = false;
 
   // Each wave owns a contiguous slice of the tiles; it keeps up to
-  // 64 * kRunGroups of this partition's runs (offset, length) in registers.
-  const uint32_t per_wave = (ntiles + kWaves - 1) / kWaves;
+  // 64 * kRunsPerLane of this partition's runs (offsets) in registers.
+  // (a multiple of 4 tiles, so that a lane's runs are one 16-byte load)
+  const uint32_t per_wave = ((ntiles + kWaves - 1) / kWaves + 3u) & ~3u;
   const uint32_t w_lo = wave * per_wave;
   const uint32_t w_hi = (w_lo + per_wave < ntiles) ? w_lo + per_wave : ntiles;
-  uint32_t r_lo[kRunGroups], r_len[kRunGroups];
-  auto load_runs = [&](uint32_t g0) {
-#pragma unroll
-    for (uint32_t g = 0; g < kRunGroups; ++g) {
-      const uint32_t t = g0 + g * 64 + lane;
-      r_lo[g] = 0;
-      r_len[g] = 0;
+  uint32_t r_lo[kRunsPerLane], r_hi[kRunsPerLane];
+  uint32_t loaded = ~0u;  // chunk of runs held in registers
+  const uint32_t stride = (pv.max_tiles + 3u) & ~3u;
+  const uint32_t* row_lo = pv.runs_t + (uint64_t)p * stride;
+  const uint32_t* row_hi = row_lo + stride;
+  auto load_runs = [&](uint32_t c0) {
+    const uint32_t t = c0 + lane * kRunsPerLane;  // a multiple of 4
+    if (pv.runs_t) {
+      // transposed table: two 16-byte loads (t + 3 < stride: inside the row)
+      uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
       if (t < w_hi) {
-        const uint32_t* offs = pv.runs + (uint64_t)t * (P + 1) + p;
-        r_lo[g] = offs[0];
-        r_len[g] = offs[1];
+        lo = *reinterpret_cast<const uint4*>(row_lo + t);
+        hi = *reinterpret_cast<const uint4*>(row_hi + t);
+      }
+      const uint32_t l4[4] = {lo.x, lo.y, lo.z, lo.w}, h4[4] = {hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+      for (uint32_t j = 0; j < kRunsPerLane; ++j) {
+        const bool in = t + j < w_hi;
+        r_lo[j] = in ? l4[j] : 0u;
+        r_hi[j] = in ? h4[j] : 0u;
+      }
+    } else {
+      // the bin pass's table: one column, read in place (the lines are
+      // shared by the neighbouring partitions an XCD runs at the same time)
+#pragma unroll
+      for (uint32_t j = 0; j < kRunsPerLane; ++j) {
+        r_lo[j] = 0;
+        r_hi[j] = 0;
+        if (t + j < w_hi) {
+          const uint32_t* offs = pv.runs + (uint64_t)(t + j) * (P + 1) + p;
+          r_lo[j] = offs[0];
+          r_hi[j] = offs[1];
+        }
       }
     }
+    loaded = c0;
+  };
+  // Calls body(at, ev, nb) for every batch of the wave's entries, in order
+  // (nb counts batches): at[q] is the staging index of the lane's q-th
+  // entry, ev[q] whether it exists (absent entries point at a tile's first
+  // entry, so that every load stays branch-free and in bounds).  A batch
+  // takes the next 64 * kEntryBatch entries of the chunk's concatenated runs.
+  auto for_each_batch = [&](auto&& body) {
+    uint32_t nb = 0;
+    for (uint32_t c0 = w_lo; c0 < w_hi; c0 += 64 * kRunsPerLane) {
+      if (loaded != c0) load_runs(c0);
+      // start of each of the lane's runs among the lane's entries (< 3 tiles)
+      // packed with the run's offset in its tile (< 2^16)
+      uint32_t pk[kRunsPerLane];
+      uint32_t lt = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < kRunsPerLane; ++j) {
+        pk[j] = (lt << 16) | r_lo[j];
+        lt += r_hi[j] - r_lo[j];
+      }
+      uint32_t inc = lt;
+#pragma unroll
+      for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += v;
+      }
+      const uint32_t excl = inc - lt;
+      const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+      const uint64_t cbase = (uint64_t)c0 * tile;
+      for (uint32_t e0 = 0; e0 < total; e0 += 64 * kEntryBatch, ++nb) {
+        bool ev[kEntryBatch];
+        uint64_t at[kEntryBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) {
+          const uint32_t e = e0 + q * 64 + lane;
+          const uint32_t a = wave_upper_bound(excl, e);
+          const uint32_t r = e - (uint32_t)__shfl((int)excl, (int)a);
+          // the last of lane a's runs that starts at or before r holds it
+          uint32_t js = 0, ps = (uint32_t)__shfl((int)pk[0], (int)a);
+#pragma unroll
+          for (uint32_t j = 1; j < kRunsPerLane; ++j) {
+            const uint32_t v = (uint32_t)__shfl((int)pk[j], (int)a);
+            if ((v >> 16) <= r) {
+              js = j;
+              ps = v;
+            }
+          }
+          ev[q] = e < total;
+          at[q] = cbase + (ev[q] ? (uint64_t)(a * kRunsPerLane + js) * tile + (ps & 0xffffu) +
+                                       (r - (ps >> 16))
+                                 : 0ull);
+        }
+        body(at, ev, nb);
+      }
+    }
+    return nb;
   };
 
   // keys first, then the first runs: both in flight together
@@ -271,7 +393,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     const uint32_t s = tid + j * kMergeThreads;
     kk[j] = s < B ? tv.keys[base + s] : kEmpty;
   }
-  load_runs(w_lo);
+  if (w_lo < w_hi) load_runs(w_lo);
 #pragma unroll
   for (uint32_t j = 0; j < kKeysPerThread; ++j) {
     const uint32_t s = tid + j * kMergeThreads;
@@ -285,62 +407,45 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   if (tid < 16) s_hist[tid] = 0;
   __syncthreads();
 
-  for (uint32_t g0 = w_lo; g0 < w_hi; g0 += 64 * kRunGroups) {
-    if (g0 != w_lo) load_runs(g0);
+  // (staging index, slot) of the lane's entries of the first kKeepBatches
+  // batches; ~0u marks an absent entry (index) or a dropped key (slot)
+  uint32_t keep_at[kKeepBatches][kEntryBatch], keep_slot[kKeepBatches][kEntryBatch];
 #pragma unroll
-    for (uint32_t g = 0; g < kRunGroups; ++g) {
-      const uint32_t len = r_len[g] - r_lo[g];
-      uint32_t inc = len;
+  for (uint32_t b = 0; b < kKeepBatches; ++b)
 #pragma unroll
-      for (uint32_t off = 1; off < 64; off <<= 1) {
-        const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
-        if (lane >= off) inc += v;
-      }
-      const uint32_t excl = inc - len;
-      const uint32_t total = (uint32_t)__shfl((int)inc, 63);
-      const uint64_t tbase = (uint64_t)(g0 + g * 64) * tile;
-      for (uint32_t e0 = 0; e0 < total; e0 += 64 * kEntryBatch) {
-        unsigned long long ek[kEntryBatch];
-        float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch];
-        bool ev[kEntryBatch];
-        uint64_t at[kEntryBatch];
+    for (uint32_t q = 0; q < kEntryBatch; ++q) keep_at[b][q] = keep_slot[b][q] = ~0u;
+
+  const uint32_t batches = for_each_batch([&](const uint64_t* at, const bool* ev, uint32_t nb) {
+    unsigned long long ek[kEntryBatch];
+    float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch];
 #pragma unroll
-        for (uint32_t q = 0; q < kEntryBatch; ++q) {
-          const uint32_t e = e0 + q * 64 + lane;
-          const uint32_t a = wave_upper_bound(excl, e);
-          const uint32_t lo_a = (uint32_t)__shfl((int)r_lo[g], (int)a);
-          const uint32_t ex_a = (uint32_t)__shfl((int)excl, (int)a);
-          ev[q] = e < total;
-          // lanes past the end read entry 0 of the tile (one shared line)
-          at[q] = tbase + (ev[q] ? (uint64_t)a * tile + lo_a + (e - ex_a) : 0ull);
-        }
+    for (uint32_t q = 0; q < kEntryBatch; ++q) {
+      ek[q] = pv.stage_key[at[q]];
+      er[q] = pv.stage_rgb[3 * at[q]];
+      eg[q] = pv.stage_rgb[3 * at[q] + 1];
+      eb[q] = pv.stage_rgb[3 * at[q] + 2];
+    }
 #pragma unroll
-        for (uint32_t q = 0; q < kEntryBatch; ++q) {
-          ek[q] = pv.stage_key[at[q]];
-          er[q] = pv.stage_rgb[3 * at[q]];
-          eg[q] = pv.stage_rgb[3 * at[q] + 1];
-          eb[q] = pv.stage_rgb[3 * at[q] + 2];
-        }
-#pragma unroll
-        for (uint32_t q = 0; q < kEntryBatch; ++q) {
-          if (!ev[q]) continue;
-          const unsigned long long key = ek[q];
-          const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
-          uint32_t slot = ~0u;
-          uint32_t i = 0;
-          for (; i < tv.max_probe; ++i) {
-            const uint32_t s = (start + i) & (B - 1);
-            unsigned long long cur = s_key[s];
-            if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
-            if (cur == kEmpty || cur == key) {
-              slot = s;
-              break;
-            }
+    for (uint32_t q = 0; q < kEntryBatch; ++q) {
+      uint32_t slot = ~0u;
+      const bool lookup_only = results && (ek[q] & kLookupOnlyBit) != 0;
+      if (lookup_only) slot = kLookupLater;
+      if (ev[q] && !lookup_only) {
+        const unsigned long long key = ek[q];
+        const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
+        uint32_t i = 0;
+        for (; i < tv.max_probe; ++i) {
+          const uint32_t s = (start + i) & (B - 1);
+          unsigned long long cur = s_key[s];
+          if (cur == kEmpty) cur = atomicCAS(&s_key[s], kEmpty, key);
+          if (cur == kEmpty || cur == key) {
+            slot = s;
+            break;
           }
-          if (slot == ~0u) {
-            atomicAdd(&s_dropped, 1u);
-            continue;
-          }
+        }
+        if (slot == ~0u) {
+          atomicAdd(&s_dropped, 1u);
+        } else {
           if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
           atomicAdd(&s_cnt[slot], 1u);
           atomicAdd(&s_sum0[slot], (double)er[q]);
@@ -348,8 +453,18 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           atomicAdd(&s_sum2[slot], (double)eb[q]);
         }
       }
+      if (results) {
+        const uint32_t a = ev[q] ? (uint32_t)at[q] : ~0u;
+#pragma unroll
+        for (uint32_t b = 0; b < kKeepBatches; ++b) {
+          if (nb == b) {
+            keep_at[b][q] = a;
+            keep_slot[b][q] = slot;
+          }
+        }
+      }
     }
-  }
+  });
   __syncthreads();
 
   // write the partition back; the old slots of a group are loaded together
@@ -406,6 +521,14 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         tv.slots[g] = nw;
         if (old[j].key != k) tv.keys[g] = k;
         ++touched;
+        if (results) {
+          // what a lookup of the cell returns from now on
+          float v[3];
+          load_state(nw, bp.dtype, v[0], v[1], v[2]);
+          s_sum0[s] = v[0];
+          s_sum1[s] = v[1];
+          s_sum2[s] = v[2];
+        }
       } else {
         Acc a = acc_old[j];
         a.n += c;
@@ -426,6 +549,60 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     if (sat) atomicAdd(&s_sat, 1u);
   }
   __syncthreads();
+
+  if (results) {
+    // slot of a key in the final LDS key table, or ~0u
+    auto find = [&](unsigned long long key) {
+      const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
+      for (uint32_t i = 0; i < tv.max_probe; ++i) {
+        const uint32_t s = (start + i) & (B - 1);
+        const unsigned long long cur = s_key[s];
+        if (cur == key) return s;
+        if (cur == kEmpty) break;
+      }
+      return ~0u;
+    };
+    // the value a lookup of the cell in slot returns (kDroppedBits if none)
+    auto put = [&](uint64_t at, uint32_t slot) {
+      float v[3] = {__uint_as_float(kDroppedBits), 0.0f, 0.0f};
+      if (slot != ~0u && s_cnt[slot] > 0) {
+        v[0] = (float)s_sum0[slot];
+        v[1] = (float)s_sum1[slot];
+        v[2] = (float)s_sum2[slot];
+      } else if (slot != ~0u) {
+        // a lookup-only entry whose cell this launch did not touch
+        const Slot sl = tv.slots[base + slot];
+        if (sl.c_old > 0) load_state(sl, bp.dtype, v[0], v[1], v[2]);
+      }
+      float* d = pv.stage_rgb + 3 * at;
+      d[0] = v[0];
+      d[1] = v[1];
+      d[2] = v[2];
+    };
+#pragma unroll
+    for (uint32_t b = 0; b < kKeepBatches; ++b) {
+#pragma unroll
+      for (uint32_t q = 0; q < kEntryBatch; ++q) {
+        if (keep_at[b][q] == ~0u) continue;
+        uint32_t slot = keep_slot[b][q];
+        if (slot == kLookupLater) slot = find(pv.stage_key[keep_at[b][q]] & ~kLookupOnlyBit);
+        put(keep_at[b][q], slot);
+      }
+    }
+    if (batches > kKeepBatches) {
+      // later batches: read the keys again and find their (final) slots
+      for_each_batch([&](const uint64_t* at, const bool* ev, uint32_t nb) {
+        if (nb < kKeepBatches) return;
+        unsigned long long ek[kEntryBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) ek[q] = pv.stage_key[at[q]];
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q)
+          if (ev[q]) put(at[q], find(ek[q] & ~kLookupOnlyBit));
+      });
+    }
+  }
+
   if (tid == 0) {
     if (s_dropped) atomicAdd(&tv.stats->dropped, (unsigned long long)s_dropped);
     if (kFused) {
@@ -441,28 +618,82 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 
 template <bool kFused>
 __global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles,
-                                                         BlendParams bp) {
-  merge_body<kFused>(tv, pv, ntiles, bp, blockIdx.x);
+                                                         BlendParams bp, int32_t results) {
+  merge_body<kFused>(tv, pv, ntiles, bp, blockIdx.x, results != 0);
 }
 
-// ------------------------------------------------------------------ cached-key lookup
-__device__ __forceinline__ void query_cached_one(const unsigned long long* rkeys, uint64_t n,
-                                                 const TableView& tv, int32_t dtype, float* out,
-                                                 uint8_t* found, uint64_t i) {
-  const unsigned long long key = rkeys[i];
-  float rgb[3];
-  const uint8_t hit = lookup_key(tv, dtype, key, rgb);
-  out[i] = rgb[0];
-  out[n + i] = rgb[1];
-  out[2 * n + i] = rgb[2];
-  if (found) found[i] = hit;
+// ------------------------------------------------------------------ unstage
+// The fused query: tile t's records take the values the merge pass left in
+// the tile's staged entries (their positions in pv.perm).  The tile's staged
+// values are read into LDS with 16-byte loads, then every thread answers
+// four consecutive records at a time (8-byte perm loads, 16-byte stores when
+// the output rows are 16-byte aligned).
+constexpr uint32_t kUnstageThreads = 512;
+
+__device__ __forceinline__ void unstage_one(const float* s_res, uint32_t count, uint32_t pos, float& r,
+                                            float& g, float& b, uint8_t& f) {
+  r = g = b = 0.0f;
+  f = 0;
+  if (pos == kNoPos || pos >= count) return;
+  const float x = s_res[3 * pos];
+  if (__float_as_uint(x) == kDroppedBits) return;
+  r = x;
+  g = s_res[3 * pos + 1];
+  b = s_res[3 * pos + 2];
+  f = 1;
 }
 
-__global__ void __launch_bounds__(256) k_query_cached(const unsigned long long* rkeys, uint64_t n,
-                                                      TableView tv, int32_t dtype, float* out,
-                                                      uint8_t* found) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) query_cached_one(rkeys, n, tv, dtype, out, found, i);
+__device__ __forceinline__ void unstage_body(const PartView& pv, uint32_t P, uint64_t n, uint32_t t,
+                                             float* out, uint8_t* found) {
+  extern __shared__ float s_res[];  // tile * 3
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t t0 = (uint64_t)t * pv.tile;
+  const uint32_t count = pv.runs[(uint64_t)t * (P + 1) + P];
+  // t0 * 12 bytes is a multiple of 16 (tiles are multiples of 512 records)
+  const float4* src4 = reinterpret_cast<const float4*>(pv.stage_rgb + 3 * t0);
+  const uint32_t nf = 3 * count, n4 = nf / 4;
+  float4* dst4 = reinterpret_cast<float4*>(s_res);
+  for (uint32_t i = tid; i < n4; i += nt) dst4[i] = src4[i];
+  for (uint32_t i = 4 * n4 + tid; i < nf; i += nt) s_res[i] = pv.stage_rgb[3 * t0 + i];
+  __syncthreads();
+  const uint64_t end = t0 + pv.tile < n ? t0 + pv.tile : n;
+  const bool vec = (n & 3u) == 0 && ((uintptr_t)out & 15u) == 0 && ((uintptr_t)found & 3u) == 0;
+  for (uint64_t i = t0 + 4ull * tid; i < end; i += 4ull * nt) {
+    float r[4], g[4], b[4];
+    uint8_t f[4];
+    if (i + 4 <= end) {
+      // i is a multiple of 4 and perm is 256-byte aligned
+      const ushort4 pp = *reinterpret_cast<const ushort4*>(pv.perm + i);
+      unstage_one(s_res, count, pp.x, r[0], g[0], b[0], f[0]);
+      unstage_one(s_res, count, pp.y, r[1], g[1], b[1], f[1]);
+      unstage_one(s_res, count, pp.z, r[2], g[2], b[2], f[2]);
+      unstage_one(s_res, count, pp.w, r[3], g[3], b[3], f[3]);
+    } else {
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t pos = i + k < end ? pv.perm[i + k] : kNoPos;
+        unstage_one(s_res, count, pos, r[k], g[k], b[k], f[k]);
+      }
+    }
+    if (vec && i + 4 <= end) {
+      *reinterpret_cast<float4*>(out + i) = make_float4(r[0], r[1], r[2], r[3]);
+      *reinterpret_cast<float4*>(out + n + i) = make_float4(g[0], g[1], g[2], g[3]);
+      *reinterpret_cast<float4*>(out + 2 * n + i) = make_float4(b[0], b[1], b[2], b[3]);
+      if (found) *reinterpret_cast<uchar4*>(found + i) = make_uchar4(f[0], f[1], f[2], f[3]);
+    } else {
+      for (int k = 0; k < 4; ++k) {
+        if (i + k >= end) break;
+        out[i + k] = r[k];
+        out[n + i + k] = g[k];
+        out[2 * n + i + k] = b[k];
+        if (found) found[i + k] = f[k];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kUnstageThreads) k_unstage(PartView pv, uint32_t P, uint64_t n, float* out,
+                                                             uint8_t* found) {
+  unstage_body(pv, P, n, blockIdx.x, out, found);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -511,7 +742,7 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
 }
 
 hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
-                        hipStream_t s) {
+                        bool results, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
@@ -521,19 +752,46 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
   hipError_t e = fuse ? lds_limit(reinterpret_cast<const void*>(&k_merge<true>), shm, &lim_f)
                       : lds_limit(reinterpret_cast<const void*>(&k_merge<false>), shm, &lim_p);
   if (e != hipSuccess) return e;
+  // staged lookup-only entries exist exactly when the bin pass wrote perm
+  if (results != (pv.perm != nullptr) || (results && !fuse)) return hipErrorInvalidValue;
   if (fuse)
-    k_merge<true><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse);
+    k_merge<true><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse, results ? 1 : 0);
   else
-    k_merge<false><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, BlendParams{});
+    k_merge<false><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, BlendParams{}, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_query_cached(const unsigned long long* rkeys, uint64_t n, const TableView& tv,
-                               int32_t dtype, float* out, uint8_t* found, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_query_cached<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rkeys, n, tv, dtype, out, found);
+static size_t unstage_lds(uint32_t tile) { return (size_t)tile * 12; }
+
+uint32_t transpose_blocks(uint32_t ntiles, uint32_t P) {
+  return ((ntiles + kTransposeDim - 1) / kTransposeDim) * ((P + 1 + kTransposeDim - 1) / kTransposeDim);
+}
+
+bool transpose_pays(uint32_t ntiles, uint32_t P) { return (uint64_t)ntiles * (P + 1) >= kTransposeMinWords; }
+
+hipError_t launch_transpose_runs(const TableView& tv, const PartView& pv, uint32_t ntiles, hipStream_t s) {
+  if (ntiles == 0 || !pv.runs_t) return hipSuccess;
+  if (ntiles > pv.max_tiles) return hipErrorInvalidValue;
+  const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
+  const dim3 grid((ntiles + kTransposeDim - 1) / kTransposeDim, (P + 1 + kTransposeDim - 1) / kTransposeDim);
+  k_transpose_runs<<<grid, kTransposeThreads, 0, s>>>(pv, P, ntiles);
   return hipGetLastError();
 }
+
+hipError_t launch_unstage(uint64_t n, const TableView& tv, const PartView& pv, float* out,
+                          uint8_t* found, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (!partition_ok(tv, pv, n) || !pv.perm) return hipErrorInvalidValue;
+  const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
+  const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
+  const size_t shm = unstage_lds(pv.tile);
+  static int lim = 0;
+  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_unstage), shm, &lim);
+  if (e != hipSuccess) return e;
+  k_unstage<<<ntiles, kUnstageThreads, shm, s>>>(pv, P, n, out, found);
+  return hipGetLastError();
+}
+
 
 // ------------------------------------------------------------------ batched sessions
 // One launch per pass covers every session: a block finds its session by
@@ -544,11 +802,23 @@ __device__ __forceinline__ uint32_t find_session(const BatchSession* ss, uint32_
   uint32_t s = 0;
   while (s + 1 < k) {
     const BatchSession& nx = ss[s + 1];
-    const uint32_t begin = which == 0 ? nx.tile_begin : (which == 1 ? nx.part_begin : nx.qblk_begin);
+    const uint32_t begin = which == 0   ? nx.tile_begin
+                           : which == 1 ? nx.part_begin
+                           : which == 2 ? nx.qblk_begin
+                                        : nx.trans_begin;
     if (begin > b) break;
     ++s;
   }
   return s;
+}
+
+__global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const BatchSession* ss, uint32_t k) {
+  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 3)];
+  const uint32_t local = blockIdx.x - S.trans_begin;
+  if (local >= S.ntrans || !S.pv.runs_t) return;
+  const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
+  const uint32_t gx = (S.ntiles + kTransposeDim - 1) / kTransposeDim;
+  transpose_body(S.pv, P, S.ntiles, local % gx, local / gx);
 }
 
 template <uint32_t kPer>
@@ -563,17 +833,21 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSessio
   const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 1)];
   const uint32_t local = blockIdx.x - S.part_begin;
   if (local >= S.nparts) return;
-  merge_body<true>(S.tv, S.pv, S.ntiles, S.bp, local);
+  merge_body<true>(S.tv, S.pv, S.ntiles, S.bp, local, S.fused_query != 0);
 }
 
+// A session whose queries are its records takes one unstage block per tile;
+// any other session one lookup block per kQueryBlock queries.
 __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession* ss, uint32_t k) {
   const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 2)];
-  const uint64_t i = (uint64_t)(blockIdx.x - S.qblk_begin) * kQueryBlock + threadIdx.x;
-  if (i >= S.nq) return;
-  if (S.cached) {
-    query_cached_one(S.pv.rkeys, S.nq, S.tv, S.bp.dtype, S.out, S.found, i);
+  const uint32_t local = blockIdx.x - S.qblk_begin;
+  if (S.fused_query) {
+    if (local < S.ntiles)
+      unstage_body(S.pv, 1u << (S.tv.log2_slots - S.tv.part_log2), S.n, local, S.out, S.found);
     return;
   }
+  const uint64_t i = (uint64_t)local * kQueryBlock + threadIdx.x;
+  if (i >= S.nq) return;
   float rgb[3];
   const uint8_t hit = lookup_key(S.tv, S.bp.dtype, query_key(S.kp, S.q, i), rgb);
   S.out[i] = rgb[0];
@@ -584,27 +858,36 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
 
 hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
   if (k == 0) return hipSuccess;
-  uint32_t tiles = 0, parts = 0, qblks = 0;
-  size_t lds_b = 0, lds_m = 0;
+  uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
+  size_t lds_b = 0, lds_m = 0, lds_q = 0;
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
     const BatchSession& S = h_ss[i];
     if (S.n == 0 || !partition_ok(S.tv, S.pv, S.n) || S.pv.tile != h_ss[0].pv.tile ||
-        S.tile_begin != tiles || S.part_begin != parts || S.qblk_begin != qblks || (S.part_begin & 7u))
+        S.tile_begin != tiles || S.part_begin != parts || S.qblk_begin != qblks || (S.part_begin & 7u) ||
+        S.trans_begin != trans ||
+        S.ntrans != (S.pv.runs_t ? transpose_blocks(S.ntiles, 1u << (S.tv.log2_slots - S.tv.part_log2)) : 0u))
       return hipErrorInvalidValue;
     const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
     const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv.part_log2);
     lds_b = lb > lds_b ? lb : lds_b;
     lds_m = lm > lds_m ? lm : lds_m;
+    if ((S.fused_query != 0) != (S.pv.perm != nullptr)) return hipErrorInvalidValue;
+    if (S.fused_query) {
+      if (S.nq != S.n || S.nqblk != S.ntiles) return hipErrorInvalidValue;
+      lds_q = unstage_lds(S.pv.tile);
+    }
     tiles += S.ntiles;
     parts += (S.nparts + 7u) & ~7u;
     qblks += S.nqblk;
+    trans += S.ntrans;
   }
-  static int lim8 = 0, lim12 = 0, lim16 = 0, lim_m = 0;
+  static int lim8 = 0, lim12 = 0, lim16 = 0, lim_m = 0, lim_q = 0;
   hipError_t e = per == 8    ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<8>), lds_b, &lim8)
                  : per == 12 ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<12>), lds_b, &lim12)
                              : lds_limit(reinterpret_cast<const void*>(&k_bin_batch<16>), lds_b, &lim16);
   if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
+  if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_query_batch), lds_q, &lim_q);
   if (e != hipSuccess) return e;
   if (per == 8)
     k_bin_batch<8><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
@@ -613,9 +896,11 @@ hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint
   else
     k_bin_batch<16><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (trans) k_transpose_batch<<<trans, kTransposeThreads, 0, s>>>(d_ss, k);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_merge_batch<<<parts, kMergeThreads, lds_m, s>>>(d_ss, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (qblks) k_query_batch<<<qblks, kQueryBlock, 0, s>>>(d_ss, k);
+  if (qblks) k_query_batch<<<qblks, kQueryBlock, lds_q, s>>>(d_ss, k);
   return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ PSF_RESET_COUNTERS, PSF_RESET_CLEAR, PSF_RESET_STATS = 1, 2, 4
 PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
 PSF_FLAG_PROBE_STATS = 1
 PSF_FLAG_TIMING = 2
-PSF_K_COUNT = 8
+PSF_FLAG_TRANSPOSE_RUNS = 4
+PSF_K_COUNT = 9
 
 REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
 QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough")

@@ -35,12 +35,16 @@ def _frame(wl, sc, it):
     return sc.generate(wl["gen"], it)
 
 
-def test_batch_equals_alone_and_oracle(env):
+@pytest.mark.parametrize("transpose", [False, True])
+def test_batch_equals_alone_and_oracle(env, transpose):
     import oracle
     torch, psf = env
     ss = _sessions()
-    alone = [psf.Table(**wl["table"]) for wl, _ in ss]
-    mixed = [psf.Table(**wl["table"]) for wl, _ in ss]
+    # transposing every session's run table covers the merge pass's other
+    # way of reading it; mixing flags covers sessions that differ in it
+    fl = [psf.PSF_FLAG_TRANSPOSE_RUNS if transpose and i % 2 == 0 else 0 for i in range(len(ss))]
+    alone = [psf.Table(**wl["table"], flags=f) for (wl, _), f in zip(ss, fl)]
+    mixed = [psf.Table(**wl["table"], flags=f) for (wl, _), f in zip(ss, fl)]
     orcs = [oracle.Oracle(**wl["table"]) for wl, _ in ss]
     batch = psf.Batch(16)
     for it in range(3):

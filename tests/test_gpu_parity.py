@@ -378,9 +378,11 @@ def test_invalid_arguments(psf, torch_cuda):
         assert lib.psf_table_bytes(ctypes.byref(c)) == 0, kw
 
 
-@pytest.mark.parametrize("bin_per", [8, 12, 16])
-@pytest.mark.parametrize("part_log2", [8, 10, 12])
-def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_log2):
+TUNABLE = [(b, p, 0) for b in (8, 12, 16) for p in (8, 10, 12)] + [(8, 11, 4), (16, 8, 4), (12, 12, 4)]
+
+
+@pytest.mark.parametrize("bin_per,part_log2,flags", TUNABLE)
+def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_log2, flags):
     """Every launch configuration the autotuner may pick gives the oracle's
     result (two fused iterations of the plain scene at reduced resolution)."""
     from synth import workloads as W
@@ -390,7 +392,7 @@ def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_lo
     # 2^20 slots keep every partition far from full even at 256 slots each
     cfg = dict(wl["table"], log2_slots=20)
     orc = _oracle(cfg)
-    t = _table(psf, cfg, insert_mode=2, bin_per=bin_per, part_log2=part_log2)
+    t = _table(psf, cfg, insert_mode=2, bin_per=bin_per, part_log2=part_log2, flags=flags)
     for it in range(2):
         rec = sc.generate(g, it)
         orc.insert(rec)
@@ -398,7 +400,70 @@ def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_lo
         out, found = t.iterate(to_device(rec))
     torch_cuda.cuda.synchronize()
     assert t.stats()["dropped"] == 0
-    compare_cells(t.export(), orc.export(), RTOL_F32, f"bin_per={bin_per} part_log2={part_log2}")
+    compare_cells(t.export(), orc.export(), RTOL_F32, f"bin_per={bin_per} part_log2={part_log2} flags={flags}")
     w_out, w_found = orc.query(rec)
     assert np.array_equal(found.cpu().numpy(), w_found)
     assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+
+
+# ----------------------------------------------------------------- fused query
+def _fused_cases():
+    # (label, config overrides, record transform)
+    def ragged(n):
+        return lambda rec: take(rec, np.arange(n) % len(rec["px"]))
+
+    def nonfinite(rec):
+        rec = {k: (None if v is None else v.copy()) for k, v in rec.items()}
+        rec["px"][::101] = np.nan
+        rec["g"][7::107] = -np.inf
+        return rec
+
+    same = lambda rec: rec  # noqa: E731
+    return [
+        ("tiny", {}, same),
+        ("n=1", {}, ragged(1)),
+        ("n=65", {}, ragged(65)),
+        ("n=8193", {}, ragged(8193)),
+        ("nonfinite", {}, nonfinite),
+        ("overflow", dict(log2_slots=8, max_probe=16), same),
+        ("max_probe=1", dict(log2_slots=12, max_probe=1), same),
+        # 16 partitions of 256 slots and 25 tiles: every wave of a merge block
+        # holds many batches, so later batches find their slots again
+        ("dense", dict(log2_slots=12, part_log2=8), ragged(100003)),
+        ("dense-transposed", dict(log2_slots=12, part_log2=8, flags=4), ragged(100003)),
+        ("transposed", dict(flags=4), same),
+        ("f16", dict(state_dtype=1), same),
+        ("bf16", dict(state_dtype=2), same),
+    ]
+
+
+@pytest.mark.parametrize("case", _fused_cases(), ids=lambda c: c[0])
+def test_fused_query_equals_lookup(psf, torch_cuda, case):
+    """psf_iterate with the records as queries answers them in the merge
+    pass; the answers must be exactly what a lookup of the same table state
+    returns, and (where no key was dropped) what the oracle returns."""
+    label, over, transform = case
+    wl, _ = _tiny(0, 0)
+    cfg = dict(wl["table"], **over)
+    t = _table(psf, cfg, insert_mode=2)
+    orc = _oracle(cfg)
+    for it in range(3):
+        _, rec = _tiny(it, 0)
+        rec = transform(rec)
+        d = to_device(rec)
+        out, found = t.iterate(d)
+        out2, found2 = t.query(d)
+        torch_cuda.cuda.synchronize()
+        a, b = out.cpu().numpy(), out2.cpu().numpy()
+        assert np.array_equal(found.cpu().numpy(), found2.cpu().numpy()), (label, it)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (label, it)
+        orc.insert(rec)
+        orc.update()
+    st = t.stats()
+    if st["dropped"] == 0:
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found), label
+        tol = RTOL_F32 if cfg.get("state_dtype", 0) == 0 else 1e-2
+        assert rel_err(out.cpu().numpy(), w_out).max() <= tol, label
+    else:
+        assert label in ("overflow", "max_probe=1", "dense", "dense-transposed"), (label, st["dropped"])
