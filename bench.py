@@ -95,6 +95,25 @@ def _dev(rec, torch):
     return {k: (None if v is None else torch.from_numpy(v).cuda()) for k, v in rec.items()}
 
 
+TUNED = {"use": True}
+
+
+def tuned(name: str) -> dict:
+    """Launch parameters the autotuner recorded for a workload (the
+    committed paper_2005_07547_amd/tuning.json), or {} with --untuned."""
+    if not TUNED["use"]:
+        return {}
+    from paper_2005_07547_amd import autotune
+    return autotune.best_params(name)
+
+
+def with_params(cfg: dict, params: dict, flags: int = 0) -> dict:
+    c = dict(cfg)
+    c.update(params)
+    c["flags"] = int(params.get("flags", 0)) | flags
+    return c
+
+
 def form_precision(torch, psf, W, iters=12):
     """Precision workload (1920x1080, 5 vertices, HDR): records/s of the fused
     iteration for FP32, FP16 and BF16 approximant storage."""
@@ -105,7 +124,7 @@ def form_precision(torch, psf, W, iters=12):
     frames = [_dev(sc.generate(wl["gen"], i), torch) for i in range(2)]
     out = {}
     for name in ("f32", "f16", "bf16"):
-        t = psf.Table(**dict(wl["table"], max_batch=n,
+        t = psf.Table(**dict(with_params(wl["table"], tuned(wl["name"])), max_batch=n,
                              state_dtype={"f32": 0, "f16": 1, "bf16": 2}[name]))
         o = torch.empty((3, n), dtype=torch.float32, device="cuda")
         f = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -127,7 +146,7 @@ def form_precision(torch, psf, W, iters=12):
                      "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
                      "saturated": st["saturated"], "dropped": st["dropped"]}
         t.close()
-    return {"workload": wl["name"], "records_per_iteration": n, "by_state": out,
+    return {"workload": wl["name"], "records_per_iteration": n, "params": tuned(wl["name"]), "by_state": out,
             "note": "error vs the binary64 oracle is asserted in tests/test_gpu_precision.py"}
 
 
@@ -144,7 +163,8 @@ def form_batched(torch, psf, W, iters=8, sessions=16):
     total = sum(ns)
     res = {}
     for mode in ("plain_per_session", "batched"):
-        tabs = [psf.Table(**dict(wl["table"], max_batch=n)) for wl, n in zip(wls, ns)]
+        tabs = [psf.Table(**dict(with_params(wl["table"], tuned("batched-16")), max_batch=n))
+                for wl, n in zip(wls, ns)]
         outs = [torch.empty((3, n), dtype=torch.float32, device="cuda") for n in ns]
         fnds = [torch.empty(n, dtype=torch.uint8, device="cuda") for n in ns]
         batch = psf.Batch(len(wls))
@@ -181,7 +201,7 @@ def form_batched(torch, psf, W, iters=8, sessions=16):
         del tabs, outs, fnds
     res["speedup_batched_over_plain"] = round(res["batched"]["records_per_s"] /
                                               res["plain_per_session"]["records_per_s"], 3)
-    return {"sessions": len(wls), "records_per_iteration": total, **res}
+    return {"sessions": len(wls), "records_per_iteration": total, "params": tuned("batched-16"), **res}
 
 
 def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
@@ -212,11 +232,11 @@ def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     return summ
 
 
-def graph_replay(torch, psf, wl, bufs, out, found, steps, n):
+def graph_replay(torch, psf, wl, bufs, out, found, steps, n, params=None):
     """The same iterations replayed from HIP graphs (one graph per input
     buffer, captured from psf_iterate on a fresh table after an eager warm-up):
     launch overhead removed."""
-    t = psf.Table(**dict(wl["table"], max_batch=max(n, 1)))
+    t = psf.Table(**dict(with_params(wl["table"], params or {}), max_batch=max(n, 1)))
     for b in bufs[:2]:
         t.iterate(b, out=out, found=found)
     torch.cuda.synchronize()
@@ -258,9 +278,12 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
     ap.add_argument("--forms", default="precision,batched,serving",
                     help="comma list of extra forms to measure (precision,batched,serving) or ''")
+    ap.add_argument("--untuned", action="store_true",
+                    help="library default launch parameters instead of the recorded tuned ones")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    TUNED["use"] = not args.untuned
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the hash path is "
@@ -302,8 +325,9 @@ def main():
     found = torch.empty(n, dtype=torch.uint8, device=dev)
     dtype_code = {"f32": psf.PSF_STATE_F32, "f16": psf.PSF_STATE_F16, "bf16": psf.PSF_STATE_BF16}[args.state]
     flags = 0 if args.no_timing else psf.PSF_FLAG_TIMING
-    table = psf.Table(**dict(wl["table"], insert_mode=args.insert_mode, state_dtype=dtype_code,
-                             flags=flags, max_batch=max(n, 1)))
+    params = tuned(wl["name"]) if args.insert_mode == psf.PSF_INSERT_AUTO else {}
+    table = psf.Table(**dict(with_params(wl["table"], params, flags), state_dtype=dtype_code,
+                             max_batch=max(n, 1), **({} if params else {"insert_mode": args.insert_mode})))
     torch.cuda.synchronize()
 
     def step(i):
@@ -369,7 +393,7 @@ def main():
         "config": {"workload": wl["name"], "records_per_iteration": n,
                    "log2_slots": wl["table"]["log2_slots"], "iterations_timed": steps,
                    "mode": "split" if args.split else "psf_iterate",
-                   "insert_mode": args.insert_mode, "pool_buffers": pool},
+                   "insert_mode": args.insert_mode, "pool_buffers": pool, "params": params},
         "p50_iter_ms": round(float(np.percentile(iter_ms, 50)), 4),
         "p99_iter_ms": round(float(np.percentile(iter_ms, 99)), 4),
         "iteration_hbm_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
@@ -381,7 +405,7 @@ def main():
     }
     table.close()
     if not args.no_graph and not args.split:
-        result["graph_replay"] = graph_replay(torch, psf, wl, bufs, out, found, args.steps, n)
+        result["graph_replay"] = graph_replay(torch, psf, wl, bufs, out, found, args.steps, n, params)
     del bufs, out, found
     torch.cuda.empty_cache()
     forms = {}

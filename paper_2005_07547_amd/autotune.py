@@ -2,8 +2,10 @@
 
 Sweeps the tunables of the partitioned insert -- records per thread of the
 binning pass (``bin_per``: tile size and LDS staging width), slots per
-partition (``part_log2``: the LDS hash width of the merge pass) -- and the
-insert strategy (partitioned vs. wave-merged direct atomics) on caller-given
+partition (``part_log2``: the LDS hash width of the merge pass), whether the
+per-tile run table is transposed before the merge (``flags`` with
+``PSF_FLAG_TRANSPOSE_RUNS``; otherwise the library decides by table size) --
+and the insert strategy (partitioned vs. wave-merged direct atomics) on caller-given
 device-resident iterations, timing whole ``psf_iterate`` calls with HIP
 events.  The result is a ranked list and the best configuration; ``tune``
 optionally records it in a JSON table keyed by workload name, which
@@ -24,6 +26,7 @@ DEFAULT_SPACE = {
     "insert_mode": [psf.PSF_INSERT_PARTITIONED],
     "bin_per": [8, 12, 16],
     "part_log2": [10, 11, 12],
+    "flags": [0, psf.PSF_FLAG_TRANSPOSE_RUNS],
 }
 
 
@@ -35,6 +38,7 @@ def candidates(space=None):
         if c.get("insert_mode") == psf.PSF_INSERT_DIRECT:
             c.pop("bin_per", None)
             c.pop("part_log2", None)
+            c.pop("flags", None)
         yield c
 
 
@@ -80,14 +84,7 @@ def tune(table_cfg: dict, bufs: list, space=None, name: str | None = None, recor
     results.sort(key=lambda r: (r.get("dropped", 0) > 0, r["ms"]))
     best = results[0]["params"]
     if record and name:
-        table = {}
-        if os.path.exists(TABLE_PATH):
-            with open(TABLE_PATH) as f:
-                table = json.load(f)
-        table[name] = {"params": best, "ms": results[0]["ms"], "n": int(bufs[0]["px"].numel()),
-                       "log2_slots": table_cfg.get("log2_slots"), "when": time.strftime("%Y-%m-%d")}
-        with open(TABLE_PATH, "w") as f:
-            json.dump(table, f, indent=1, sort_keys=True)
+        _record(name, best, results[0]["ms"], int(bufs[0]["px"].numel()), table_cfg.get("log2_slots"))
     return best, results
 
 
@@ -99,3 +96,104 @@ def best_params(name: str, default=None) -> dict:
         if name in table:
             return dict(table[name]["params"])
     return dict(default or {})
+
+
+def time_batch(table_cfgs: list, params: dict, frames: list, warmup: int = 2, iters: int = 4):
+    """Median ms per batched iteration of the sessions (table_cfgs[i] with
+    frames[i], a list of device frames cycled per iteration), every session
+    using params."""
+    import torch
+    ns = [int(f[0]["px"].numel()) for f in frames]
+    tabs = [psf.Table(**dict(c, **params, max_batch=n)) for c, n in zip(table_cfgs, ns)]
+    outs = [torch.empty((3, n), dtype=torch.float32, device="cuda") for n in ns]
+    fnds = [torch.empty(n, dtype=torch.uint8, device="cuda") for n in ns]
+    batch = psf.Batch(len(tabs))
+    try:
+        def step(k):
+            batch.iterate(tabs, [f[k % len(f)] for f in frames], outs=outs, founds=fnds)
+
+        for k in range(warmup):
+            step(k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(iters)]
+        torch.cuda.synchronize()
+        for k in range(iters):
+            ev[k][0].record()
+            step(warmup + k)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        dropped = sum(t.stats()["dropped"] for t in tabs)
+    finally:
+        for t in tabs:
+            t.close()
+        batch.close()
+    return {"ms": ms[len(ms) // 2], "min_ms": ms[0], "dropped": dropped}
+
+
+def _record(name, best, ms, n, log2_slots, path=None):
+    path = path or TABLE_PATH
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table[name] = {"params": best, "ms": ms, "n": n, "log2_slots": log2_slots,
+                   "when": time.strftime("%Y-%m-%d")}
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
+def main():
+    """Tune the named synthetic workloads on the GPU and record the winners:
+    python -m paper_2005_07547_amd.autotune [--workloads plain,precision,batched] [--record]"""
+    import argparse
+
+    import torch
+
+    from synth import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workloads", default="plain,precision,batched")
+    ap.add_argument("--record", action="store_true")
+    ap.add_argument("--table", default=None, help="JSON file to record into (default: tuning.json here)")
+    args = ap.parse_args()
+    global TABLE_PATH
+    if args.table:
+        TABLE_PATH = args.table
+
+    def dev(rec):
+        return {k: (None if v is None else torch.from_numpy(v).cuda()) for k, v in rec.items()}
+
+    for name in [w for w in args.workloads.split(",") if w]:
+        if name == "batched":
+            wls = W.batched_sessions(16)
+            frames = []
+            for wl in wls:
+                sc = W.make_scene(wl)
+                frames.append([dev(sc.generate(wl["gen"], i)) for i in range(2)])
+            space = {"bin_per": [8, 16], "part_log2": [10, 11, 12],
+                     "flags": [0, psf.PSF_FLAG_TRANSPOSE_RUNS]}
+            results = []
+            for c in candidates(dict(space, insert_mode=[psf.PSF_INSERT_PARTITIONED])):
+                r = time_batch([wl["table"] for wl in wls], c, frames)
+                r["params"] = c
+                results.append(r)
+                print(f"batched {c} -> {r['ms']:.3f} ms (dropped {r['dropped']})", flush=True)
+            results.sort(key=lambda r: (r["dropped"] > 0, r["ms"]))
+            print("BEST batched", results[0], flush=True)
+            if args.record:
+                _record("batched-16", results[0]["params"], results[0]["ms"],
+                        sum(int(f[0]["px"].numel()) for f in frames), None)
+            del frames
+        else:
+            wl = getattr(W, name)()
+            sc = W.make_scene(wl)
+            bufs = [dev(sc.generate(wl["gen"], i)) for i in range(4)]
+            best, res = tune(wl["table"], bufs, name=wl["name"], record=args.record,
+                             log=lambda m: print(name, m, flush=True))
+            print("BEST", name, best, res[0]["ms"], flush=True)
+            del bufs
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main()

@@ -2,6 +2,8 @@
 
 * ``stats``: turn a ``--kernel-trace --stats`` kernel_stats.csv into a short
   Markdown table (with the command that produced it);
+* ``traffic-md``: the same record as a Markdown table beside the kernels'
+  algorithmic bytes;
 * ``traffic``: combine two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE, KiB
   per dispatch) with the same counters taken on a plain 1 GiB device copy,
   into per-launch HBM bytes of each kernel, scaled so that the copy reads
@@ -79,6 +81,26 @@ def stats_markdown(stats_csv: str, title: str, command: str, note: str = "") -> 
     return "\n".join(lines) + "\n"
 
 
+def traffic_markdown(rec: dict, title: str, commands: list, algorithmic: dict) -> str:
+    """Markdown table of a traffic record: counter KiB, scaled HBM bytes and,
+    where given, the kernel's algorithmic bytes per launch (by short name)."""
+    lines = [f"# {title}", "", "Counters (KiB per dispatch), each in a rocprofv3 run of its own:", ""]
+    lines += [f"    {c}" for c in commands]
+    lines += ["", f"Calibration on a 1 GiB device copy: FETCH_SIZE x {rec['fetch_scale']:.4f}, "
+              f"WRITE_SIZE x {rec['write_scale']:.4f} give the bytes the copy moves.", "",
+              "| Kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes (scaled) | Algorithmic bytes | Ratio |",
+              "|---|---|---|---|---|---|"]
+    for name, v in sorted(rec["kernels"].items(), key=lambda kv: -kv[1]["bytes"]):
+        short = name.split("(")[0].split("::")[-1]
+        base = short.split("<")[0]
+        a = algorithmic.get(base)
+        lines.append(f"| {short} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['bytes'] / 1e6:.1f} MB | "
+                     + (f"{a / 1e6:.1f} MB | {v['bytes'] / a:.2f} |" if a else "- | - |"))
+    lines += ["", f"Kernel source digest: `{rec['digest']}` (bench.py reports `traffic` only while the "
+              "kernel sources still have this digest)."]
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -93,9 +115,21 @@ def main():
         b.add_argument(f"--{name}", required=True)
     b.add_argument("--command", default="")
     b.add_argument("--out", required=True)
+    c = sub.add_parser("traffic-md")
+    c.add_argument("--json", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("--algorithmic", default="{}", help="JSON {kernel: bytes per launch}")
+    c.add_argument("--out", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
         md = stats_markdown(_find(args.dir, "*kernel_stats.csv"), args.title, args.command, args.note)
+        with open(args.out, "w") as f:
+            f.write(md)
+    elif args.cmd == "traffic-md":
+        with open(args.json) as f:
+            rec = json.load(f)
+        md = traffic_markdown(rec, args.title, args.command, json.loads(args.algorithmic))
         with open(args.out, "w") as f:
             f.write(md)
     else:

@@ -12,9 +12,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_autotune_candidates_cover_the_space():
     from paper_2005_07547_amd import autotune, psf
     c = list(autotune.candidates())
-    assert len(c) == 9
+    assert len(c) == 18
     assert {x["bin_per"] for x in c} == {8, 12, 16}
     assert {x["part_log2"] for x in c} == {10, 11, 12}
+    assert {x["flags"] for x in c} == {0, psf.PSF_FLAG_TRANSPOSE_RUNS}
     d = list(autotune.candidates({"insert_mode": [psf.PSF_INSERT_DIRECT], "bin_per": [8]}))
     assert d == [{"insert_mode": psf.PSF_INSERT_DIRECT}]
 
