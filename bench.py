@@ -329,7 +329,7 @@ def main():
     params = tuned(wl["name"]) if args.insert_mode == psf.PSF_INSERT_AUTO else {}
     steps = args.steps
 
-    def timed_pass(flags):
+    def timed_pass(flags, steps=steps):
         """Warm up, then time exactly `steps` iterations of a fresh table
         (wall clock around the loop, HIP events around every step)."""
         table = psf.Table(**dict(with_params(wl["table"], params, flags), state_dtype=dtype_code,
@@ -362,7 +362,7 @@ def main():
         el = time.perf_counter() - t0
         iter_ms = np.array([x.elapsed_time(y) for x, y in ev])
         st1 = table.stats()
-        kt = table.kernel_times() if flags else {}
+        kt = table.kernel_times() if flags & psf.PSF_FLAG_TIMING else {}
         table.close()
         return el, iter_ms, st0, st1, kt
 
@@ -371,10 +371,16 @@ def main():
     # with HIP events on the library's stream for the per-kernel times and
     # the roofline
     elapsed, iter_ms, st0, st1, _ = timed_pass(0)
-    kt, inst_ms = {}, None
+    kt, inst_ms, probes = {}, None, None
     if not args.no_timing:
         el2, _, _, _, kt = timed_pass(psf.PSF_FLAG_TIMING)
         inst_ms = round(el2 / steps * 1e3, 4)
+        # probes each inserted sample needed in its partition (last bin: 16+),
+        # from a short pass of its own (the histogram costs LDS atomics)
+        _, _, p0, p1, _ = timed_pass(psf.PSF_FLAG_PROBE_STATS, min(steps, 4))
+        probes = [int(b - a) for a, b in zip(p0["probe_hist"], p1["probe_hist"])]
+        while len(probes) > 1 and probes[-1] == 0:
+            probes.pop()
     touched = (st1["touched_total"] - st0["touched_total"]) / max(1, st1["updates"] - st0["updates"])
     ab = algorithmic_bytes(n, touched)
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])} for k, v in kt.items()}
@@ -417,6 +423,7 @@ def main():
         "dropped": st1["dropped"],
         "kernels": kernels,
         "instrumented_ms_per_step": inst_ms,
+        "probe_hist": probes,
         "roofline": roofline,
     }
     if not args.no_graph and not args.split:

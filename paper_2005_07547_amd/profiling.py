@@ -2,6 +2,8 @@
 
 * ``stats``: turn a ``--kernel-trace --stats`` kernel_stats.csv into a short
   Markdown table (with the command that produced it);
+* ``counters-md``: any other counters (L2 hits, LDS bank conflicts, waves)
+  per kernel as a Markdown table;
 * ``traffic-md``: the same record as a Markdown table beside the kernels'
   algorithmic bytes;
 * ``traffic``: combine two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE, KiB
@@ -81,6 +83,26 @@ def stats_markdown(stats_csv: str, title: str, command: str, note: str = "") -> 
     return "\n".join(lines) + "\n"
 
 
+def counters_markdown(dirs: list, title: str, commands: list, kernels: list) -> str:
+    """Mean per dispatch of every counter found in the given --pmc output
+    directories, one row per kernel whose name contains one of `kernels`."""
+    merged = collections.defaultdict(dict)
+    for d in dirs:
+        for k, cs in counter_means(d).items():
+            merged[k].update(cs)
+    names = sorted({c for cs in merged.values() for c in cs})
+    lines = [f"# {title}", "", "Counters (mean per dispatch), one rocprofv3 run per group:", ""]
+    lines += [f"    {c}" for c in commands]
+    lines += ["", "| Kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+    for k in sorted(merged):
+        short = k.split("(")[0].split("::")[-1]
+        if kernels and not any(x in short for x in kernels):
+            continue
+        lines.append(f"| {short} | " + " | ".join(
+            f"{merged[k][c]:.4g}" if c in merged[k] else "-" for c in names) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def traffic_markdown(rec: dict, title: str, commands: list, algorithmic: dict) -> str:
     """Markdown table of a traffic record: counter KiB, scaled HBM bytes and,
     where given, the kernel's algorithmic bytes per launch (by short name)."""
@@ -115,6 +137,12 @@ def main():
         b.add_argument(f"--{name}", required=True)
     b.add_argument("--command", default="")
     b.add_argument("--out", required=True)
+    m = sub.add_parser("counters-md")
+    m.add_argument("--dir", action="append", required=True)
+    m.add_argument("--title", required=True)
+    m.add_argument("--command", action="append", default=[])
+    m.add_argument("--kernels", default="k_bin,k_merge,k_unstage,k_transpose")
+    m.add_argument("--out", required=True)
     c = sub.add_parser("traffic-md")
     c.add_argument("--json", required=True)
     c.add_argument("--title", required=True)
@@ -124,6 +152,10 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         md = stats_markdown(_find(args.dir, "*kernel_stats.csv"), args.title, args.command, args.note)
+        with open(args.out, "w") as f:
+            f.write(md)
+    elif args.cmd == "counters-md":
+        md = counters_markdown(args.dir, args.title, args.command, [k for k in args.kernels.split(",") if k])
         with open(args.out, "w") as f:
             f.write(md)
     elif args.cmd == "traffic-md":
