@@ -347,7 +347,7 @@ def main():
         for i in range(args.warmup):
             step(i)
         torch.cuda.synchronize()
-        if flags:
+        if flags & psf.PSF_FLAG_TIMING:
             table.kernel_times(reset=True)
         st0 = table.stats()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
