@@ -206,6 +206,57 @@ def form_batched(torch, psf, W, iters=8, sessions=16):
     return {"sessions": len(wls), "records_per_iteration": total, "params": tuned("batched-16"), **res}
 
 
+EST_IN_BYTES = 17 * 4      # position, normal, two directions, roughness, g, w/p
+EST_OUT_BYTES = 12 + 1     # estimate rgb, applied flag
+EST_CELL_BYTES = 2 * 24    # two cell lookups (key + state)
+
+
+def form_estimate(torch, psf, W, iters=32, warm_frames=4):
+    """Two fields per cell and the fused estimator epilogue on the plain
+    workload: both fields are learned over a few frames, then every vertex of
+    a frame gets the control-variate estimate (beta 0.75) in one call."""
+    import numpy as np
+    wl = W.plain()
+    sc = W.make_scene(wl)
+    n = W.records_per_iteration(wl)
+    params = tuned(wl["name"])
+    oe = psf.Table(**dict(with_params(wl["table"], params, psf.PSF_FLAG_TIMING), max_batch=n))
+    fl = psf.Table(**dict(with_params(W.fl_table(wl["table"]), params), max_batch=n))
+    a = None
+    for i in range(warm_frames):
+        rec = sc.generate(wl["gen"], i)
+        args, flr = W.estimator_inputs(rec, wl["gen"])
+        oe.iterate(_dev(rec, torch))
+        fl.iterate(_dev(flr, torch))
+        a = _dev(args, torch)
+    out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    app = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        psf.estimate(oe, fl, a, psf.PSF_EST_CV, 0.75, out=out, applied=app)
+    torch.cuda.synchronize()
+    oe.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        psf.estimate(oe, fl, a, psf.PSF_EST_CV, 0.75, out=out, applied=app)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = oe.kernel_times()
+    launches, total = kt.get("estimate", (0, 0.0))
+    avg_ms = total / max(1, launches)
+    per_launch = n * (EST_IN_BYTES + EST_OUT_BYTES + EST_CELL_BYTES)
+    ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    res = {"workload": wl["name"], "vertices": n, "mode": "control variate, beta 0.75",
+           "vertices_per_s": round(n * iters / el, 1), "ms_per_call": round(el / iters * 1e3, 4),
+           "applied_fraction": round(float(app.float().mean()), 4),
+           "roofline": {"bound": "hbm", "kernel": "estimate", "achieved": None if ach is None else round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5)}}
+    oe.close()
+    fl.close()
+    return res
+
+
 def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     """Poisson arrivals at 20/s, resolutions lognormal around 720p, 32-128
     iterations each, 1 spp, 4 vertices; continuous batching under an HBM
@@ -278,8 +329,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
-    ap.add_argument("--forms", default="precision,batched,serving",
-                    help="comma list of extra forms to measure (precision,batched,serving) or ''")
+    ap.add_argument("--forms", default="precision,batched,serving,estimate",
+                    help="comma list of extra forms to measure (precision,batched,serving,estimate) or ''")
     ap.add_argument("--untuned", action="store_true",
                     help="library default launch parameters instead of the recorded tuned ones")
     ap.add_argument("--copy-calib", action="store_true",
@@ -432,7 +483,8 @@ def main():
     torch.cuda.empty_cache()
     forms = {}
     for name in [f for f in args.forms.split(",") if f]:
-        fn = {"precision": form_precision, "batched": form_batched, "serving": form_serving}[name]
+        fn = {"precision": form_precision, "batched": form_batched, "serving": form_serving,
+              "estimate": form_estimate}[name]
         print(f"# measuring form {name}", file=sys.stderr, flush=True)
         forms[name] = fn(torch, psf, W)
         torch.cuda.empty_cache()

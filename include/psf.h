@@ -100,7 +100,8 @@ enum {
   PSF_K_QUERY = 6,
   PSF_K_BATCH = 7,
   PSF_K_TRANSPOSE = 8,
-  PSF_K_COUNT = 9
+  PSF_K_ESTIMATE = 9,
+  PSF_K_COUNT = 10
 };
 
 /*
@@ -278,6 +279,50 @@ psf_status psf_batch_create(uint32_t max_sessions, psf_batch** out);
 psf_status psf_batch_destroy(psf_batch* b);
 
 psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, uint32_t k, psf_stream stream);
+
+/* Estimators built on two fields (Sec. 2.5): t_oe holds the approximant of
+ * L_o\e (outgoing radiance minus emission, the field Algorithm 2 tracks),
+ * keyed on the outgoing direction; t_fli holds the approximant of f L_i
+ * (incoming radiance times the BSDF), keyed on the incoming (sampled)
+ * direction.  For the latter the key should carry the direction at every
+ * vertex: create t_fli with rough_thr = +INFINITY and pass roughness.
+ *
+ * At each of n path vertices (SoA device arrays, caller-owned) the call
+ * looks up L~o\e(x, w_o) in t_oe and f~L_i(x, w_i) in t_fli, as psf_query
+ * would, and combines them with the vertex's Monte Carlo sample
+ * g = L_i(x, w_i) f(w_i, w_o) (gr, gg, gb) and its weight wp = w / p_perp
+ * (MIS weight over the projected-solid-angle density of w_i):
+ *
+ *   PSF_EST_CV      (Sec. 4.2, Eq. 25; param = beta):
+ *                   wp * (g - beta f~L_i) + beta L~o\e
+ *   PSF_EST_BIASED  (Sec. 5, Eq. 28; param = gamma):
+ *                   gamma * wp * (g - f~L_i) + L~o\e
+ *
+ * The known integral L~o\e of the control variate is added once, outside
+ * the wp factor (the unbiased form; the printed estimators put it inside).
+ * Where either cell is missing (or not yet blended) the vertex gets the
+ * plain estimate wp * g and d_out_applied (nullable, n bytes) is 0; else 1.
+ * d_out_rgb receives 3*n floats, SoA.  Arithmetic is binary32 in the order
+ * written, without contraction.  Reads the state left by each table's last
+ * completed temporal update.  param must be finite. */
+enum {
+  PSF_EST_CV = 0,
+  PSF_EST_BIASED = 1
+};
+
+typedef struct psf_estimate_args {
+  const float *px, *py, *pz;     /* vertex position */
+  const float *nx, *ny, *nz;     /* shading normal */
+  const float *oox, *ooy, *ooz;  /* outgoing direction w_o (key of t_oe) */
+  const float *oix, *oiy, *oiz;  /* incoming, sampled direction w_i (key of t_fli) */
+  const float *rough;            /* nullable: all vertices diffuse */
+  const float *gr, *gg, *gb;     /* sample g = L_i f */
+  const float *wp;               /* w / p_perp */
+} psf_estimate_args;
+
+psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_estimate_args* a, uint64_t n,
+                        int32_t mode, float param, float* d_out_rgb, uint8_t* d_out_applied,
+                        psf_stream stream);
 
 /* Per-kernel timing (tables created with PSF_FLAG_TIMING): for each kernel
  * kind k < PSF_K_COUNT, launches[k] and total_ms[k] (host arrays of

@@ -8,7 +8,9 @@ arrays through ctypes.  It imports nothing from the HIP package.
 Sections followed: Sec. 2.1 Eq. 5-6 (counts and weighted means per basis
 function), Sec. 2.4 Eq. 10-11 (temporal blend, counter reset), Sec. 2.6
 (spatio-directional hashing; the key specification is this project's, written
-out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state).
+out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state),
+and, for the two-field estimators, Sec. 2.5, Sec. 4.2 (Eq. 25) and Sec. 5
+(Eq. 28) in ``estimate`` below (plain numpy in binary64 over the lookups).
 """
 from __future__ import annotations
 
@@ -167,3 +169,51 @@ class Oracle:
         a = np.zeros(3, dtype=np.uint64)
         self._lib.orc_counters(self._h, a[0:].ctypes.data, a[1:].ctypes.data, a[2:].ctypes.data)
         return {"skipped": int(a[0]), "coord_overflow": int(a[1]), "inserted": int(a[2])}
+
+
+# --------------------------------------------------------------------------
+# Estimators on two fields (Sec. 4.2, Eq. 25; Sec. 5, Eq. 28).
+EST_CV, EST_BIASED = 0, 1
+
+
+def estimate(orc_oe: Oracle, orc_fli: Oracle, a: dict, mode: int, param: float):
+    """Control-variate (mode EST_CV, param = beta) or biased (EST_BIASED,
+    param = gamma) estimate of the outgoing radiance minus emission at every
+    vertex of `a`.
+
+    At a vertex x with outgoing direction w_o and sampled incoming direction
+    w_i the control variate is h = f~L_i(x, w_i) (looked up in orc_fli, keyed
+    on w_i) and its known integral is L~o\\e(x, w_o) (looked up in orc_oe,
+    keyed on w_o).  With the vertex's sample g = L_i f and weight
+    wp = w / p_perp:
+
+      Sec. 4.2 (Eq. 25):  wp (g - beta h) + beta L~o\\e
+      Sec. 5 (Eq. 28):    gamma wp (g - h) + L~o\\e   (beta = 1, corrector scaled)
+
+    Reading: the known integral is added once, outside the wp factor (the
+    estimate is then unbiased for any beta; the printed formulas place it
+    inside the bracket that is divided by the density).  Where either cell
+    is missing or not yet blended the vertex keeps the plain estimate wp g.
+    Binary64 throughout; param is taken at binary32, as the library receives
+    it.  Returns (estimate (3, n) float64, applied (n,) uint8).
+    """
+    n = int(np.asarray(a["px"]).shape[0])
+    base = {k: a[k] for k in ("px", "py", "pz", "nx", "ny", "nz")}
+    base["rough"] = a.get("rough")
+    zeros = np.zeros(n, dtype=np.float32)
+    qo = dict(base, ox=a.get("oox", zeros), oy=a.get("ooy", zeros), oz=a.get("ooz", zeros))
+    qi = dict(base, ox=a.get("oix", zeros), oy=a.get("oiy", zeros), oz=a.get("oiz", zeros))
+    L, fo = orc_oe.query(qo)
+    h, fi = orc_fli.query(qi)
+    g = np.stack([np.asarray(a[k], dtype=np.float64) for k in ("gr", "gg", "gb")])
+    w = np.asarray(a["wp"], dtype=np.float64)
+    p = float(np.float32(param))
+    if mode == EST_CV:
+        e = w * (g - p * h) + p * L
+    elif mode == EST_BIASED:
+        e = p * (w * (g - h)) + L
+    else:
+        raise ValueError("mode must be EST_CV or EST_BIASED")
+    both = (fo != 0) & (fi != 0)
+    e = np.where(both[None, :], e, w * g)
+    return e, both.astype(np.uint8)

@@ -722,6 +722,37 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
   return PSF_OK;
 }
 
+PSF_API psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_estimate_args* a, uint64_t n,
+                                int32_t mode, float param, float* d_out_rgb, uint8_t* d_out_applied,
+                                psf_stream stream) {
+  if (!t_oe || !t_fli) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!a) return fail(PSF_INVALID_ARGUMENT, "estimate arguments are NULL");
+  if (!a->px || !a->py || !a->pz || !a->nx || !a->ny || !a->nz)
+    return fail(PSF_INVALID_ARGUMENT, "position and normal arrays are required");
+  if (a->rough && (!a->oox || !a->ooy || !a->ooz || !a->oix || !a->oiy || !a->oiz))
+    return fail(PSF_INVALID_ARGUMENT, "direction arrays are required when roughness is given");
+  if (!a->gr || !a->gg || !a->gb || !a->wp) return fail(PSF_INVALID_ARGUMENT, "sample and weight arrays are required");
+  if (mode != PSF_EST_CV && mode != PSF_EST_BIASED) return fail(PSF_INVALID_ARGUMENT, "mode must be CV or BIASED");
+  if (!std::isfinite(param)) return fail(PSF_INVALID_ARGUMENT, "param must be finite");
+  if (!d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t_oe->last = s;
+  t_fli->last = s;
+  psf::EstPtrs ep;
+  ep.qo = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oox, a->ooy, a->ooz, a->rough};
+  ep.qi = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oix, a->oiy, a->oiz, a->rough};
+  ep.gr = a->gr;
+  ep.gg = a->gg;
+  ep.gb = a->gb;
+  ep.wp = a->wp;
+  hipError_t e = timed(t_oe, PSF_K_ESTIMATE, s, [&] {
+    return psf::launch_estimate(ep, n, t_oe->kp, t_oe->tv, t_oe->cfg.state_dtype, t_fli->kp, t_fli->tv,
+                                t_fli->cfg.state_dtype, mode, param, d_out_rgb, d_out_applied, s);
+  });
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "estimate launch");
+}
+
 PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* total_ms, int reset) {
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
   if (!t->timer) return fail(PSF_NOT_SUPPORTED, "table was created without PSF_FLAG_TIMING");
@@ -740,7 +771,7 @@ PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* to
 
 PSF_API const char* psf_kernel_name(uint32_t k) {
   static const char* names[PSF_K_COUNT] = {"keys", "insert_direct", "bin", "merge", "merge_blend",
-                                           "update", "query", "batch", "transpose"};
+                                           "update", "query", "batch", "transpose", "estimate"};
   return k < PSF_K_COUNT ? names[k] : "";
 }
 

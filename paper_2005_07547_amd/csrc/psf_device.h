@@ -267,6 +267,40 @@ __device__ __forceinline__ uint8_t lookup_key(const TableView& tv, int32_t dtype
   return 0;
 }
 
+// The same lookup split in two, so that the first probes of several
+// lookups can be in flight together: lookup_first issues the load of the
+// key's first slot (any key, also kEmpty: the slot is then ignored),
+// lookup_finish resolves it and probes further only if needed.
+struct PendingLookup {
+  uint64_t key;
+  ProbeSeq ps;
+  Slot first;
+};
+
+__device__ __forceinline__ PendingLookup lookup_first(const TableView& tv, uint64_t key) {
+  PendingLookup l;
+  l.key = key;
+  l.ps = probe_seq(key, tv.log2_slots, tv.part_log2);
+  l.first = tv.slots[l.ps.at(0)];
+  return l;
+}
+
+__device__ __forceinline__ uint8_t lookup_finish(const TableView& tv, int32_t dtype, const PendingLookup& l,
+                                                 float rgb[3]) {
+  rgb[0] = rgb[1] = rgb[2] = 0.0f;
+  if (l.key == kEmpty) return 0;
+  Slot sl = l.first;
+  for (uint32_t j = 0;;) {
+    if (sl.key == l.key) {
+      if (sl.c_old == 0) return 0;
+      load_state(sl, dtype, rgb[0], rgb[1], rgb[2]);
+      return 1;
+    }
+    if (sl.key == kEmpty || ++j >= tv.max_probe) return 0;
+    sl = tv.slots[l.ps.at(j)];
+  }
+}
+
 // Key of query i of a structure-of-arrays query set (kEmpty if rejected).
 template <class Q>
 __device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, uint64_t i) {

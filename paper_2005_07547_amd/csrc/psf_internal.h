@@ -40,6 +40,16 @@ hipError_t launch_insert_direct(const RecPtrs& rec, uint64_t n, const KeyParams&
 hipError_t launch_update(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s);
 hipError_t launch_query(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv,
                         int32_t dtype, float* out, uint8_t* found, hipStream_t s);
+// Two-field estimator (control variate or biased): the vertex keyed twice,
+// on the outgoing direction (qo, table o) and on the incoming one (qi,
+// table i); both share the position, normal and roughness arrays.
+struct EstPtrs {
+  QryPtrs qo, qi;
+  const float *gr, *gg, *gb, *wp;
+};
+hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, const TableView& tv_o,
+                           int32_t dt_o, const KeyParams& kp_i, const TableView& tv_i, int32_t dt_i,
+                           int32_t mode, float param, float* out, uint8_t* applied, hipStream_t s);
 hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s);
 hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);

@@ -217,6 +217,44 @@ __global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams 
   if (found) found[i] = hit;
 }
 
+// ------------------------------------------------------------------ two-field estimators
+// Sec. 4.2 (Eq. 25) and Sec. 5 (Eq. 28): the control variate h = f~L_i(x,
+// w_i) has the known integral L~o\e(x, w_o).  mode 0: wp (g - beta h) +
+// beta L; mode 1: gamma wp (g - h) + L.  Either cell missing: wp g.
+__global__ void __launch_bounds__(256) k_estimate(EstPtrs a, uint64_t n, KeyParams kp_o, TableView tv_o,
+                                                  int32_t dt_o, KeyParams kp_i, TableView tv_i,
+                                                  int32_t dt_i, int32_t mode, float param, float* out,
+                                                  uint8_t* applied) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float L[3], h[3];
+  // both first probes in flight together
+  const PendingLookup lo = lookup_first(tv_o, query_key(kp_o, a.qo, i));
+  const PendingLookup li = lookup_first(tv_i, query_key(kp_i, a.qi, i));
+  const uint8_t fo = lookup_finish(tv_o, dt_o, lo, L);
+  const uint8_t fi = lookup_finish(tv_i, dt_i, li, h);
+  const float g[3] = {a.gr[i], a.gg[i], a.gb[i]};
+  const float w = a.wp[i];
+  const bool both = fo && fi;
+  float e[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!both) {
+      e[c] = w * g[c];
+    } else if (mode == 0) {
+      const float corr = w * (g[c] - param * h[c]);
+      e[c] = corr + param * L[c];
+    } else {
+      const float corr = param * (w * (g[c] - h[c]));
+      e[c] = corr + L[c];
+    }
+  }
+  out[i] = e[0];
+  out[n + i] = e[1];
+  out[2 * n + i] = e[2];
+  if (applied) applied[i] = both ? 1 : 0;
+}
+
 // ------------------------------------------------------------------ reset / init
 __global__ void k_clear(TableView tv, uint64_t nslots) {
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
@@ -314,6 +352,15 @@ hipError_t launch_update(const TableView& tv, const BlendParams& bp, uint64_t ns
 hipError_t launch_query(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv,
                         int32_t dtype, float* out, uint8_t* found, hipStream_t s) {
   k_query<<<grid_for(n, 256), 256, 0, s>>>(q, n, kp, tv, dtype, out, found);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, const TableView& tv_o,
+                           int32_t dt_o, const KeyParams& kp_i, const TableView& tv_i, int32_t dt_i,
+                           int32_t mode, float param, float* out, uint8_t* applied, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_estimate<<<grid_for(n, 256), 256, 0, s>>>(a, n, kp_o, tv_o, dt_o, kp_i, tv_i, dt_i, mode, param, out,
+                                              applied);
   return hipGetLastError();
 }
 

@@ -23,10 +23,13 @@ PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
 PSF_FLAG_PROBE_STATS = 1
 PSF_FLAG_TIMING = 2
 PSF_FLAG_TRANSPOSE_RUNS = 4
-PSF_K_COUNT = 9
+PSF_K_COUNT = 10
+PSF_EST_CV, PSF_EST_BIASED = 0, 1
 
 REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
 QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough")
+EST_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "oox", "ooy", "ooz", "oix", "oiy", "oiz", "rough",
+              "gr", "gg", "gb", "wp")
 
 
 class PsfError(RuntimeError):
@@ -54,6 +57,10 @@ class psf_records(ctypes.Structure):
 
 class psf_queries(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in QRY_FIELDS]
+
+
+class psf_estimate_args(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in EST_FIELDS]
 
 
 class psf_stats(ctypes.Structure):
@@ -92,6 +99,8 @@ EXPORTS = [
     ("psf_batch_create", ctypes.c_int, [_u32, _P(_vp)]),
     ("psf_batch_destroy", ctypes.c_int, [_vp]),
     ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
+    ("psf_estimate", ctypes.c_int, [_vp, _vp, _P(psf_estimate_args), _u64, ctypes.c_int32, ctypes.c_float,
+                                    _vp, _vp, _vp]),
     ("psf_kernel_times", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     ("psf_kernel_name", ctypes.c_char_p, [_u32]),
     ("psf_last_error", ctypes.c_char_p, []),
@@ -289,6 +298,27 @@ class Table:
         order = np.argsort(keys[:c], kind="stable")
         return {"keys": keys[:c][order], "n_new": n_new[:c][order], "c_old": c_old[:c][order],
                 "L": rgb[:, :c][:, order]}
+
+
+def estimate(t_oe, t_fli, a: dict, mode: int, param: float, out=None, applied=None):
+    """psf_estimate: control-variate (mode PSF_EST_CV, param beta) or biased
+    (PSF_EST_BIASED, param gamma) estimate at every vertex of a (device
+    float32 arrays keyed as EST_FIELDS; rough may be None).  Returns
+    (out (3, n), applied (n,))."""
+    import torch
+    n = int(a["px"].numel())
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    if applied is None:
+        applied = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s = psf_estimate_args()
+    for f in EST_FIELDS:
+        v = a.get(f)
+        setattr(s, f, None if v is None else _ptr(_device_f32(v, f)))
+    lib = load()
+    _check(lib.psf_estimate(t_oe.handle, t_fli.handle, ctypes.byref(s), n, int(mode), float(param),
+                            ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_ptr(applied)), current_stream()))
+    return out, applied
 
 
 class Batch:

@@ -109,3 +109,60 @@ def records_per_iteration(wl) -> int:
 
 def make_scene(wl) -> Scene:
     return Scene(**wl["scene"])
+
+
+def estimator_inputs(rec: dict, gen: dict) -> tuple:
+    """Inputs of the two-field estimators for the records of one iteration
+    (depth-major, `gen` the generator parameters that made them).
+
+    The sampled incoming direction at a vertex is the direction to the
+    vertex one depth further along the same pixel's path (the last depth
+    takes the mirror of the outgoing direction about the normal); the
+    vertex's sample g is the next vertex's value (the last depth its own) and
+    its weight w / p_perp a deterministic value in [pi/2, 3 pi/2).  Returns
+    (args, fl_records): args keyed as the estimator expects, fl_records the
+    same vertices keyed on the incoming direction with value g (the samples
+    of the f L_i field).  Roughness is passed through; when the records have
+    none it is 1 (diffuse under the outgoing field's threshold, directional
+    under the f L_i field's infinite one)."""
+    n = int(rec["px"].shape[0])
+    per = int(gen["width"]) * int(gen["height"]) * int(gen.get("spp", 1))
+    verts = n // per
+    f64 = np.float64
+    p = np.stack([rec["px"], rec["py"], rec["pz"]]).astype(f64)
+    nn = np.stack([rec["nx"], rec["ny"], rec["nz"]]).astype(f64)
+    wo = np.stack([rec["ox"], rec["oy"], rec["oz"]]).astype(f64)
+    wi = np.empty_like(p)
+    g = np.stack([rec["r"], rec["g"], rec["b"]]).astype(np.float32)
+    for d in range(verts):
+        cur = slice(d * per, (d + 1) * per)
+        if d + 1 < verts:
+            nxt = slice((d + 1) * per, (d + 2) * per)
+            v = p[:, nxt] - p[:, cur]
+            g[:, cur] = g[:, nxt]
+        else:
+            v = 2.0 * np.sum(nn[:, cur] * wo[:, cur], axis=0) * nn[:, cur] - wo[:, cur]
+        ln = np.sqrt(np.sum(v * v, axis=0))
+        bad = ~(ln > 1e-12)
+        v[:, bad] = nn[:, cur][:, bad]
+        ln[bad] = 1.0
+        wi[:, cur] = v / ln
+    wi = wi.astype(np.float32)
+    k = np.arange(n, dtype=f64)
+    wp = (np.pi * (0.5 + np.mod(k * 0.6180339887498949, 1.0))).astype(np.float32)
+    rough = rec.get("rough")
+    rough = np.ones(n, dtype=np.float32) if rough is None else rough
+    args = {"px": rec["px"], "py": rec["py"], "pz": rec["pz"], "nx": rec["nx"], "ny": rec["ny"],
+            "nz": rec["nz"], "oox": rec["ox"], "ooy": rec["oy"], "ooz": rec["oz"],
+            "oix": wi[0].copy(), "oiy": wi[1].copy(), "oiz": wi[2].copy(), "rough": rough,
+            "gr": g[0].copy(), "gg": g[1].copy(), "gb": g[2].copy(), "wp": wp}
+    fl = {"px": rec["px"], "py": rec["py"], "pz": rec["pz"], "nx": rec["nx"], "ny": rec["ny"],
+          "nz": rec["nz"], "ox": args["oix"], "oy": args["oiy"], "oz": args["oiz"],
+          "r": args["gr"], "g": args["gg"], "b": args["gb"], "rough": rough}
+    return args, fl
+
+
+def fl_table(table: dict) -> dict:
+    """Configuration of the f L_i field beside a table of the outgoing field:
+    the same grid, with the (incoming) direction in every key."""
+    return dict(table, rough_thr=float("inf"))

@@ -45,6 +45,7 @@ def test_host_side_validation_without_gpu():
     assert lib.psf_iterate_batch(None, None, 0, None) == psf.PSF_OK
     assert lib.psf_iterate_batch(None, None, 2, None) == psf.PSF_INVALID_ARGUMENT
     assert lib.psf_batch_destroy(None) == psf.PSF_OK
+    assert lib.psf_estimate(None, None, None, 4, 0, 1.0, None, None, None) == psf.PSF_INVALID_ARGUMENT
     assert lib.psf_version().startswith(b"psf")
 
 
@@ -58,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no host C compiler")
     structs = {"psf_config": psf.psf_config, "psf_records": psf.psf_records,
                "psf_queries": psf.psf_queries, "psf_stats": psf.psf_stats,
-               "psf_session": psf.psf_session}
+               "psf_session": psf.psf_session, "psf_estimate_args": psf.psf_estimate_args}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psf.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
