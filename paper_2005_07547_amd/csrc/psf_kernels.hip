@@ -221,38 +221,52 @@ __global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams 
 // Sec. 4.2 (Eq. 25) and Sec. 5 (Eq. 28): the control variate h = f~L_i(x,
 // w_i) has the known integral L~o\e(x, w_o).  mode 0: wp (g - beta h) +
 // beta L; mode 1: gamma wp (g - h) + L.  Either cell missing: wp g.
-__global__ void __launch_bounds__(256) k_estimate(EstPtrs a, uint64_t n, KeyParams kp_o, TableView tv_o,
-                                                  int32_t dt_o, KeyParams kp_i, TableView tv_i,
-                                                  int32_t dt_i, int32_t mode, float param, float* out,
-                                                  uint8_t* applied) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float L[3], h[3];
-  // both first probes in flight together
-  const PendingLookup lo = lookup_first(tv_o, query_key(kp_o, a.qo, i));
-  const PendingLookup li = lookup_first(tv_i, query_key(kp_i, a.qi, i));
-  const uint8_t fo = lookup_finish(tv_o, dt_o, lo, L);
-  const uint8_t fi = lookup_finish(tv_i, dt_i, li, h);
-  const float g[3] = {a.gr[i], a.gg[i], a.gb[i]};
-  const float w = a.wp[i];
-  const bool both = fo && fi;
-  float e[3];
+constexpr uint32_t kEstThreads = 256, kEstPerThread = 1;
+
+__global__ void __launch_bounds__(kEstThreads) k_estimate(EstPtrs a, uint64_t n, KeyParams kp_o,
+                                                          TableView tv_o, int32_t dt_o, KeyParams kp_i,
+                                                          TableView tv_i, int32_t dt_i, int32_t mode,
+                                                          float param, float* out, uint8_t* applied) {
+  // kEstPerThread vertices per thread: all their first probes (two per
+  // vertex) are in flight together; indices past the end read the last
+  // vertex and write nothing
+  const uint64_t i0 = (uint64_t)blockIdx.x * (kEstThreads * kEstPerThread) + threadIdx.x;
+  PendingLookup lo[kEstPerThread], li[kEstPerThread];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (!both) {
-      e[c] = w * g[c];
-    } else if (mode == 0) {
-      const float corr = w * (g[c] - param * h[c]);
-      e[c] = corr + param * L[c];
-    } else {
-      const float corr = param * (w * (g[c] - h[c]));
-      e[c] = corr + L[c];
-    }
+  for (uint32_t v = 0; v < kEstPerThread; ++v) {
+    const uint64_t i = i0 + (uint64_t)v * kEstThreads;
+    const uint64_t ic = i < n ? i : n - 1;
+    lo[v] = lookup_first(tv_o, query_key(kp_o, a.qo, ic));
+    li[v] = lookup_first(tv_i, query_key(kp_i, a.qi, ic));
   }
-  out[i] = e[0];
-  out[n + i] = e[1];
-  out[2 * n + i] = e[2];
-  if (applied) applied[i] = both ? 1 : 0;
+#pragma unroll
+  for (uint32_t v = 0; v < kEstPerThread; ++v) {
+    const uint64_t i = i0 + (uint64_t)v * kEstThreads;
+    if (i >= n) break;
+    float L[3], h[3];
+    const uint8_t fo = lookup_finish(tv_o, dt_o, lo[v], L);
+    const uint8_t fi = lookup_finish(tv_i, dt_i, li[v], h);
+    const float g[3] = {a.gr[i], a.gg[i], a.gb[i]};
+    const float w = a.wp[i];
+    const bool both = fo && fi;
+    float e[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (!both) {
+        e[c] = w * g[c];
+      } else if (mode == 0) {
+        const float corr = w * (g[c] - param * h[c]);
+        e[c] = corr + param * L[c];
+      } else {
+        const float corr = param * (w * (g[c] - h[c]));
+        e[c] = corr + L[c];
+      }
+    }
+    out[i] = e[0];
+    out[n + i] = e[1];
+    out[2 * n + i] = e[2];
+    if (applied) applied[i] = both ? 1 : 0;
+  }
 }
 
 // ------------------------------------------------------------------ reset / init
@@ -359,8 +373,8 @@ hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, 
                            int32_t dt_o, const KeyParams& kp_i, const TableView& tv_i, int32_t dt_i,
                            int32_t mode, float param, float* out, uint8_t* applied, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_estimate<<<grid_for(n, 256), 256, 0, s>>>(a, n, kp_o, tv_o, dt_o, kp_i, tv_i, dt_i, mode, param, out,
-                                              applied);
+  k_estimate<<<grid_for(n, kEstThreads * kEstPerThread), kEstThreads, 0, s>>>(a, n, kp_o, tv_o, dt_o, kp_i, tv_i,
+                                                                             dt_i, mode, param, out, applied);
   return hipGetLastError();
 }
 
