@@ -151,13 +151,19 @@ typedef struct psf_config {
  * ox..oz is the outgoing direction omega_o (pointing back along the path,
  * Algorithm 1); it is read only for glossy vertices.  rough may be NULL
  * (every vertex diffuse).  r, g, b is the sample value assembled by the
- * caller (the path tail estimate of Eq. 3 / Eq. 9). */
+ * caller (the path tail estimate of Eq. 3 / Eq. 9).  footprint may be NULL;
+ * otherwise it is the width of the path's footprint at each vertex (Sec.
+ * 2.3 selects the hierarchy level by footprint) and the level is the
+ * largest l <= max_level with 2^(e_min + l) <= footprint (0 below 2^e_min)
+ * instead of the camera-distance rule; a non-finite or non-positive
+ * footprint rejects the record like a non-finite position. */
 typedef struct psf_records {
   const float *px, *py, *pz;
   const float *nx, *ny, *nz;
   const float *ox, *oy, *oz;
   const float *r, *g, *b;
   const float *rough;
+  const float *footprint;
 } psf_records;
 
 /* Query vertices: the same fields without a sample value. */
@@ -166,6 +172,7 @@ typedef struct psf_queries {
   const float *nx, *ny, *nz;
   const float *ox, *oy, *oz;
   const float *rough;
+  const float *footprint;
 } psf_queries;
 
 typedef struct psf_stats {
@@ -318,6 +325,7 @@ typedef struct psf_estimate_args {
   const float *rough;            /* nullable: all vertices diffuse */
   const float *gr, *gg, *gb;     /* sample g = L_i f */
   const float *wp;               /* w / p_perp */
+  const float *footprint;        /* nullable: levels as in psf_records */
 } psf_estimate_args;
 
 psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_estimate_args* a, uint64_t n,

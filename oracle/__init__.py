@@ -25,11 +25,11 @@ _lib = None
 
 ALPHA_PAPER, ALPHA_CONST, ALPHA_LINEAR = 0, 1, 2
 RESET_COUNTERS, RESET_CLEAR = 1, 2
-FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
+FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
 
 
 class _Records(ctypes.Structure):
-    _fields_ = [("f", ctypes.c_void_p * 13)]
+    _fields_ = [("f", ctypes.c_void_p * 14)]
 
 
 def build(force: bool = False) -> str:
@@ -200,6 +200,7 @@ def estimate(orc_oe: Oracle, orc_fli: Oracle, a: dict, mode: int, param: float):
     n = int(np.asarray(a["px"]).shape[0])
     base = {k: a[k] for k in ("px", "py", "pz", "nx", "ny", "nz")}
     base["rough"] = a.get("rough")
+    base["footprint"] = a.get("footprint")
     zeros = np.zeros(n, dtype=np.float32)
     qo = dict(base, ox=a.get("oox", zeros), oy=a.get("ooy", zeros), oz=a.get("ooz", zeros))
     qi = dict(base, ox=a.get("oix", zeros), oy=a.get("oiy", zeros), oz=a.get("oiz", zeros))

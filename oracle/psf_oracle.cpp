@@ -105,6 +105,22 @@ int level_of(const Config& c, float px, float py, float pz) {
   return lvl;
 }
 
+// Level from a path footprint (the width a path covers at the vertex; Sec.
+// 2.3 selects hierarchy levels by footprint): the largest l with
+// 2^(e_min + l) <= footprint, i.e. floor(log2(footprint)) - e_min, clamped
+// to [0, max_level].  floor(log2) of a binary32 value is its exponent field
+// (subnormals: taken as -127, far below any level).
+int level_of_footprint(const Config& c, float fp) {
+  uint32_t bits;
+  std::memcpy(&bits, &fp, sizeof bits);
+  int field = (int)((bits >> 23) & 0xffu);
+  int e = (field == 0) ? -127 : field - 127;
+  int lvl = e - c.e_min;
+  if (lvl < 0) lvl = 0;
+  if (lvl > c.max_level) lvl = c.max_level;
+  return lvl;
+}
+
 // Grid coordinate floor(p * 2^-(e_min + lvl)); reports whether it lies
 // outside the signed 16-bit range that the key stores.  The returned value is
 // taken modulo 2^16 by the caller.
@@ -158,18 +174,20 @@ struct KeyResult {
   uint64_t key;
 };
 
-// rough may be null (all vertices diffuse).
+// rough may be null (all vertices diffuse); fp may be null (level from the
+// camera distance), else it must be finite and positive.
 KeyResult key_of(const Config& c, float px, float py, float pz, float nx, float ny, float nz,
-                 float ox, float oy, float oz, const float* rough) {
+                 float ox, float oy, float oz, const float* rough, const float* fp) {
   KeyResult r{false, false, 0};
   if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return r;
+  if (fp && !(std::isfinite(*fp) && *fp > 0.0f)) return r;
   bool glossy = false;
   if (rough) {
     if (!std::isfinite(*rough)) return r;
     glossy = (*rough < c.rough_thr);
     if (glossy && !finite3(ox, oy, oz)) return r;
   }
-  int lvl = level_of(c, px, py, pz);
+  int lvl = fp ? level_of_footprint(c, *fp) : level_of(c, px, py, pz);
   int shift = c.e_min + lvl;
   bool ovf = false;
   int64_t ix = grid_coord(px, shift, &ovf);
@@ -210,10 +228,11 @@ double alpha_of(const Config& c, uint64_t n_new, uint64_t c_old) {
 
 extern "C" {
 
-// Record arrays: 13 pointers px,py,pz,nx,ny,nz,ox,oy,oz,r,g,b,rough.  Any of
-// ox..oz, r..b and rough may be null where not used (rough null = diffuse).
+// Record arrays: 14 pointers px,py,pz,nx,ny,nz,ox,oy,oz,r,g,b,rough,footprint.
+// Any of ox..oz, r..b, rough and footprint may be null where not used (rough
+// null = diffuse, footprint null = level from the camera distance).
 struct orc_records {
-  const float* f[13];
+  const float* f[14];
 };
 
 void* orc_create(const float* cam, float kappa, int e_min, int max_level, int normal_bins_log2,
@@ -240,7 +259,7 @@ static KeyResult key_at(const Config& c, const orc_records* r, uint64_t i) {
   const float* const* f = r->f;
   float ox = f[6] ? f[6][i] : 0.0f, oy = f[7] ? f[7][i] : 0.0f, oz = f[8] ? f[8][i] : 0.0f;
   return key_of(c, f[0][i], f[1][i], f[2][i], f[3][i], f[4][i], f[5][i], ox, oy, oz,
-                f[12] ? &f[12][i] : nullptr);
+                f[12] ? &f[12][i] : nullptr, f[13] ? &f[13][i] : nullptr);
 }
 
 // Keys of n records; invalid (skipped) records get all-ones.  overflow[i]

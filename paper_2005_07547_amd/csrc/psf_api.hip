@@ -218,15 +218,15 @@ bool qry_ok(const psf_queries* q, std::string* why) {
 
 psf::RecPtrs rec_ptrs(const psf_records* r) {
   return psf::RecPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz,
-                      r->r,  r->g,  r->b,  r->rough};
+                      r->r,  r->g,  r->b,  r->rough, r->footprint};
 }
 
 psf::QryPtrs qry_ptrs(const psf_queries* q) {
-  return psf::QryPtrs{q->px, q->py, q->pz, q->nx, q->ny, q->nz, q->ox, q->oy, q->oz, q->rough};
+  return psf::QryPtrs{q->px, q->py, q->pz, q->nx, q->ny, q->nz, q->ox, q->oy, q->oz, q->rough, q->footprint};
 }
 
 psf::QryPtrs qry_from_rec(const psf_records* r) {
-  return psf::QryPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz, r->rough};
+  return psf::QryPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz, r->rough, r->footprint};
 }
 
 uint64_t nslots(const psf_table* t) { return 1ull << t->cfg.log2_slots; }
@@ -284,7 +284,7 @@ psf_status do_update(psf_table* t, hipStream_t s) {
 
 bool same_vertices(const psf_records* r, const psf_queries* q) {
   return r->px == q->px && r->py == q->py && r->pz == q->pz && r->nx == q->nx && r->ny == q->ny &&
-         r->nz == q->nz && r->rough == q->rough &&
+         r->nz == q->nz && r->rough == q->rough && r->footprint == q->footprint &&
          (!r->rough || (r->ox == q->ox && r->oy == q->oy && r->oz == q->oz));
 }
 
@@ -740,8 +740,8 @@ PSF_API psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_est
   t_oe->last = s;
   t_fli->last = s;
   psf::EstPtrs ep;
-  ep.qo = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oox, a->ooy, a->ooz, a->rough};
-  ep.qi = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oix, a->oiy, a->oiz, a->rough};
+  ep.qo = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oox, a->ooy, a->ooz, a->rough, a->footprint};
+  ep.qi = psf::QryPtrs{a->px, a->py, a->pz, a->nx, a->ny, a->nz, a->oix, a->oiy, a->oiz, a->rough, a->footprint};
   ep.gr = a->gr;
   ep.gg = a->gg;
   ep.gb = a->gb;

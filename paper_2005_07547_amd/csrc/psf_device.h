@@ -131,6 +131,17 @@ __device__ __forceinline__ int32_t cell_level(const KeyParams& kp, float px, flo
   return lvl < 0 ? 0 : (lvl > kp.max_level ? kp.max_level : lvl);
 }
 
+// Level from a path footprint (the world-space width a path covers at the
+// vertex, the quantity the paper selects levels by in Sec. 2.3): the largest
+// l with 2^(e_min + l) <= footprint, clamped to [0, max_level], read off the
+// binary32 exponent (subnormals count as 2^-127).
+__device__ __forceinline__ int32_t footprint_level(const KeyParams& kp, float fp) {
+  const int32_t biased = (int32_t)((__float_as_uint(fp) >> 23) & 0xffu);
+  const int32_t e = biased ? biased - 127 : -127;
+  const int32_t lvl = e - kp.e_min;
+  return lvl < 0 ? 0 : (lvl > kp.max_level ? kp.max_level : lvl);
+}
+
 // floor(p * 2^-shift) modulo 2^16, flagging values outside [-2^15, 2^15).
 __device__ __forceinline__ uint32_t grid16(float p, int32_t shift, bool& ovf) {
   float f = floorf(ldexpf(p, -shift));
@@ -164,18 +175,22 @@ __device__ __forceinline__ uint32_t octa_bin(float x, float y, float z, int32_t 
 
 // Cell key of one vertex.  Returns false for rejected (non-finite) input.
 // has_rough is false when the caller supplied no roughness array (every
-// vertex diffuse); the direction is read only for glossy vertices.
+// vertex diffuse); the direction is read only for glossy vertices.  With a
+// footprint (has_fp) the level comes from it (it must be finite and > 0),
+// else from the camera distance.
 __device__ __forceinline__ bool cell_key(const KeyParams& kp, float px, float py, float pz, float nx,
                                          float ny, float nz, float ox, float oy, float oz,
-                                         bool has_rough, float rough, uint64_t& key, bool& ovf) {
+                                         bool has_rough, float rough, bool has_fp, float fp,
+                                         uint64_t& key, bool& ovf) {
   if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return false;
+  if (has_fp && !(__builtin_isfinite(fp) && fp > 0.0f)) return false;
   bool glossy = false;
   if (has_rough) {
     if (!__builtin_isfinite(rough)) return false;
     glossy = rough < kp.rough_thr;
     if (glossy && !finite3(ox, oy, oz)) return false;
   }
-  const int32_t lvl = cell_level(kp, px, py, pz);
+  const int32_t lvl = has_fp ? footprint_level(kp, fp) : cell_level(kp, px, py, pz);
   const int32_t shift = kp.e_min + lvl;
   ovf = false;
   const uint64_t ix = grid16(px, shift, ovf);
@@ -307,10 +322,11 @@ __device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, u
   const bool hr = q.rough != nullptr;
   const float ro = hr ? q.rough[i] : 0.0f;
   const bool gl = hr && ro < kp.rough_thr;
+  const bool hf = q.footprint != nullptr;
   uint64_t key;
   bool ovf;
   if (!cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
-                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, key, ovf))
+                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, hf, hf ? q.footprint[i] : 0.0f, key, ovf))
     return kEmpty;
   return key;
 }

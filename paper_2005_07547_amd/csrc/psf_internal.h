@@ -10,11 +10,11 @@
 namespace psf {
 
 struct RecPtrs {
-  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *r, *g, *b, *rough;
+  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *r, *g, *b, *rough, *footprint;
 };
 
 struct QryPtrs {
-  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *rough;
+  const float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *rough, *footprint;
 };
 
 // Partitioned-insert working buffers of one table.

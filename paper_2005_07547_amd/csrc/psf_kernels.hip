@@ -64,9 +64,10 @@ __global__ void __launch_bounds__(256) k_keys(RecPtrs rec, uint64_t n, KeyParams
   bool ovf;
   const bool hr = rec.rough != nullptr;
   const bool g = hr && rec.rough[i] < kp.rough_thr;
+  const bool hf = rec.footprint != nullptr;
   const bool ok = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
                            g ? rec.ox[i] : 0.0f, g ? rec.oy[i] : 0.0f, g ? rec.oz[i] : 0.0f, hr,
-                           hr ? rec.rough[i] : 0.0f, key, ovf);
+                           hr ? rec.rough[i] : 0.0f, hf, hf ? rec.footprint[i] : 0.0f, key, ovf);
   out[i] = ok ? key : kEmpty;
 }
 
@@ -103,9 +104,10 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
     r = rec.r[i];
     g = rec.g[i];
     b = rec.b[i];
+    const bool hf = rec.footprint != nullptr;
     valid = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
-                     gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro,
-                     key, ovf);
+                     gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro, hf,
+                     hf ? rec.footprint[i] : 0.0f, key, ovf);
     valid = valid && finite3(r, g, b);
     skip = !valid;
   }

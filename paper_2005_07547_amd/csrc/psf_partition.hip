@@ -78,7 +78,9 @@ __device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_
 // every record knows its place, the tile's staging buffer (tile * 12 bytes:
 // keys, then rgb triples), so that both global writes of the partition-
 // sorted tile are coalesced.
-template <uint32_t kPer>
+// kFp: the records carry footprints (their level rule); a separate
+// instantiation keeps the load and its registers out of the common case.
+template <uint32_t kPer, bool kFp>
 __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
                                          const TableView& tv, const PartView& pv, uint32_t tile) {
   extern __shared__ uint32_t s_dyn_bin[];
@@ -108,6 +110,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
 #pragma unroll
   for (uint32_t j0 = 0; j0 < kPer; j0 += kLoad) {
     float f[kLoad][13];
+    float fp[kLoad];
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint64_t i = t0 + (uint64_t)(j0 + q) * kBinThreads + tid;
@@ -125,6 +128,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       f[q][10] = rec.g[ic];
       f[q][11] = rec.b[ic];
       f[q][12] = p_ro[ic];
+      fp[q] = kFp ? rec.footprint[ic] : 0.0f;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
@@ -135,7 +139,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       bool ovf = false;
       uint64_t k;
       const bool kv = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
-                               f[q][7], f[q][8], hr, f[q][12], k, ovf);
+                               f[q][7], f[q][8], hr, f[q][12], kFp, fp[q], k, ovf);
       const bool sv = finite3(f[q][9], f[q][10], f[q][11]);
       if (!(kv && sv)) ++n_skip;
       // a record whose sample is rejected but whose key is valid is still a
@@ -195,10 +199,10 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
 }
 
-template <uint32_t kPer>
+template <uint32_t kPer, bool kFp>
 __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
                                                      TableView tv, PartView pv) {
-  bin_body<kPer>(rec, n, kp, tv, pv, blockIdx.x);
+  bin_body<kPer, kFp>(rec, n, kp, tv, pv, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ run table transpose
@@ -719,6 +723,16 @@ static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
          bin_per_ok(pv.tile / kBinThreads) && (1u << (tv.log2_slots - tv.part_log2)) <= kTouchEntries;
 }
 
+template <uint32_t kPer, bool kFp>
+static hipError_t launch_bin_t(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
+                               const PartView& pv, size_t shm, uint32_t ntiles, hipStream_t s) {
+  static int lim = 0;  // one per instantiation
+  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin<kPer, kFp>), shm, &lim);
+  if (e != hipSuccess) return e;
+  k_bin<kPer, kFp><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
                       const PartView& pv, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -727,18 +741,15 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
   const uint32_t per = pv.tile / kBinThreads;
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = bin_lds(P, per);
-  static int lim8 = 0, lim12 = 0, lim16 = 0;
-  hipError_t e = per == 8    ? lds_limit(reinterpret_cast<const void*>(&k_bin<8>), shm, &lim8)
-                 : per == 12 ? lds_limit(reinterpret_cast<const void*>(&k_bin<12>), shm, &lim12)
-                             : lds_limit(reinterpret_cast<const void*>(&k_bin<16>), shm, &lim16);
-  if (e != hipSuccess) return e;
+  const bool fp = rec.footprint != nullptr;
   if (per == 8)
-    k_bin<8><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
-  else if (per == 12)
-    k_bin<12><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
-  else
-    k_bin<16><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
-  return hipGetLastError();
+    return fp ? launch_bin_t<8, true>(rec, n, kp, tv, pv, shm, ntiles, s)
+              : launch_bin_t<8, false>(rec, n, kp, tv, pv, shm, ntiles, s);
+  if (per == 12)
+    return fp ? launch_bin_t<12, true>(rec, n, kp, tv, pv, shm, ntiles, s)
+              : launch_bin_t<12, false>(rec, n, kp, tv, pv, shm, ntiles, s);
+  return fp ? launch_bin_t<16, true>(rec, n, kp, tv, pv, shm, ntiles, s)
+            : launch_bin_t<16, false>(rec, n, kp, tv, pv, shm, ntiles, s);
 }
 
 hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
@@ -821,12 +832,15 @@ __global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const Bat
   transpose_body(S.pv, P, S.ntiles, local % gx, local / gx);
 }
 
-template <uint32_t kPer>
+template <uint32_t kPer, bool kFp>
 __global__ void __launch_bounds__(kBinThreads) k_bin_batch(const BatchSession* ss, uint32_t k) {
   const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 0)];
   const uint32_t local = blockIdx.x - S.tile_begin;
   if (local >= S.ntiles) return;
-  bin_body<kPer>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+  if (kFp && S.rec.footprint)
+    bin_body<kPer, true>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+  else
+    bin_body<kPer, false>(S.rec, S.n, S.kp, S.tv, S.pv, local);
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, uint32_t k) {
@@ -856,10 +870,21 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
   if (S.found) S.found[i] = hit;
 }
 
+template <uint32_t kPer, bool kFp>
+static hipError_t launch_bin_batch_t(const BatchSession* d_ss, uint32_t k, uint32_t tiles, size_t lds,
+                                     hipStream_t s) {
+  static int lim = 0;  // one per instantiation
+  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin_batch<kPer, kFp>), lds, &lim);
+  if (e != hipSuccess) return e;
+  k_bin_batch<kPer, kFp><<<tiles, kBinThreads, lds, s>>>(d_ss, k);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
   if (k == 0) return hipSuccess;
   uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   size_t lds_b = 0, lds_m = 0, lds_q = 0;
+  bool fp = false;  // any session's records carry footprints
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
     const BatchSession& S = h_ss[i];
@@ -877,24 +902,23 @@ hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint
       if (S.nq != S.n || S.nqblk != S.ntiles) return hipErrorInvalidValue;
       lds_q = unstage_lds(S.pv.tile);
     }
+    fp = fp || S.rec.footprint != nullptr;
     tiles += S.ntiles;
     parts += (S.nparts + 7u) & ~7u;
     qblks += S.nqblk;
     trans += S.ntrans;
   }
-  static int lim8 = 0, lim12 = 0, lim16 = 0, lim_m = 0, lim_q = 0;
-  hipError_t e = per == 8    ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<8>), lds_b, &lim8)
-                 : per == 12 ? lds_limit(reinterpret_cast<const void*>(&k_bin_batch<12>), lds_b, &lim12)
-                             : lds_limit(reinterpret_cast<const void*>(&k_bin_batch<16>), lds_b, &lim16);
-  if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
+  static int lim_m = 0, lim_q = 0;
+  hipError_t e = fp ? (per == 8    ? launch_bin_batch_t<8, true>(d_ss, k, tiles, lds_b, s)
+                       : per == 12 ? launch_bin_batch_t<12, true>(d_ss, k, tiles, lds_b, s)
+                                   : launch_bin_batch_t<16, true>(d_ss, k, tiles, lds_b, s))
+                    : (per == 8    ? launch_bin_batch_t<8, false>(d_ss, k, tiles, lds_b, s)
+                       : per == 12 ? launch_bin_batch_t<12, false>(d_ss, k, tiles, lds_b, s)
+                                   : launch_bin_batch_t<16, false>(d_ss, k, tiles, lds_b, s));
+  if (e != hipSuccess) return e;
+  e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
   if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_query_batch), lds_q, &lim_q);
   if (e != hipSuccess) return e;
-  if (per == 8)
-    k_bin_batch<8><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
-  else if (per == 12)
-    k_bin_batch<12><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
-  else
-    k_bin_batch<16><<<tiles, kBinThreads, lds_b, s>>>(d_ss, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (trans) k_transpose_batch<<<trans, kTransposeThreads, 0, s>>>(d_ss, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;

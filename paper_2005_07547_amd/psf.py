@@ -26,10 +26,10 @@ PSF_FLAG_TRANSPOSE_RUNS = 4
 PSF_K_COUNT = 10
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 
-REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
-QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough")
+REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
+QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough", "footprint")
 EST_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "oox", "ooy", "ooz", "oix", "oiy", "oiz", "rough",
-              "gr", "gg", "gb", "wp")
+              "gr", "gg", "gb", "wp", "footprint")
 
 
 class PsfError(RuntimeError):

@@ -166,3 +166,19 @@ def fl_table(table: dict) -> dict:
     """Configuration of the f L_i field beside a table of the outgoing field:
     the same grid, with the (incoming) direction in every key."""
     return dict(table, rough_thr=float("inf"))
+
+
+def footprints(rec: dict, wl: dict, spread: float = 1.0) -> np.ndarray:
+    """A path-footprint width per record (input of the footprint level rule):
+    k_s * pixel angle * camera distance, the width the camera-distance rule
+    assumes, times a deterministic factor 2^u with u in [-spread, spread)
+    standing in for the footprint growth a renderer tracks along a path."""
+    g = wl["gen"]
+    cam = np.asarray(g["cam"], dtype=np.float64)
+    theta = 2.0 * math.tan(math.radians(g["fov_y_deg"]) / 2.0) / float(g["height"])
+    k_s = math.sqrt(wl["table"]["kappa"]) * 2.0 ** wl["table"]["e_min"] / theta if wl["table"]["kappa"] > 0 else 1.0
+    p = np.stack([rec["px"], rec["py"], rec["pz"]]).astype(np.float64)
+    d = np.sqrt(np.sum((p - cam[:, None]) ** 2, axis=0))
+    k = np.arange(d.shape[0], dtype=np.float64)
+    u = (np.mod(k * 0.7548776662466927, 1.0) * 2.0 - 1.0) * spread
+    return (k_s * theta * d * np.exp2(u)).astype(np.float32)

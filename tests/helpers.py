@@ -6,7 +6,7 @@ import os
 import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough")
+FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
 
 
 def golden_rows(name):
@@ -22,7 +22,7 @@ def golden_rows(name):
 
 def records(n, **cols):
     """Record dict of n entries; unspecified fields default to a +z normal,
-    +z direction, unit radiance and no roughness array."""
+    +z direction, unit radiance and no roughness or footprint array."""
     base = {"px": 0.0, "py": 0.0, "pz": 0.0, "nx": 0.0, "ny": 0.0, "nz": 1.0,
             "ox": 0.0, "oy": 0.0, "oz": 1.0, "r": 1.0, "g": 1.0, "b": 1.0}
     out = {}
@@ -39,7 +39,7 @@ def records(n, **cols):
 def concat(recs):
     out = {}
     for k in FIELDS:
-        parts = [r[k] for r in recs]
+        parts = [r.get(k) for r in recs]
         out[k] = None if any(p is None for p in parts) else np.concatenate(parts)
     return out
 

@@ -30,7 +30,7 @@ def _check(psf, oracle, oe_t, fl_t, oe_o, fl_o, a, mode, param):
     want, w_app = oracle.estimate(oe_o, fl_o, a, mode, param)
     assert np.array_equal(applied.cpu().numpy(), w_app)
     # scale of the terms the estimate adds up, from the oracle's lookups
-    base = {k: a[k] for k in ("px", "py", "pz", "nx", "ny", "nz", "rough")}
+    base = {k: a.get(k) for k in ("px", "py", "pz", "nx", "ny", "nz", "rough", "footprint")}
     L, _ = oe_o.query(dict(base, ox=a["oox"], oy=a["ooy"], oz=a["ooz"]))
     h, _ = fl_o.query(dict(base, ox=a["oix"], oy=a["oiy"], oz=a["oiz"]))
     g = np.stack([a["gr"], a["gg"], a["gb"]]).astype(np.float64)

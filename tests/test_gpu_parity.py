@@ -467,3 +467,53 @@ def test_fused_query_equals_lookup(psf, torch_cuda, case):
         assert rel_err(out.cpu().numpy(), w_out).max() <= tol, label
     else:
         assert label in ("overflow", "max_probe=1", "dense", "dense-transposed"), (label, st["dropped"])
+
+
+# ----------------------------------------------------------------- footprint levels
+def test_footprint_keys_bit_exact(psf, torch_cuda):
+    import struct
+    rows = golden_rows("footprint_levels.txt")
+    rng = np.random.default_rng(12)
+    fp = np.concatenate([
+        np.array([struct.unpack(">f", bytes.fromhex(r[2]))[0] for r in rows], dtype=np.float32),
+        np.exp2(rng.uniform(-20, 20, 5000)).astype(np.float32),
+        np.exp2(np.arange(-20, 21)).astype(np.float32),
+        np.nextafter(np.exp2(np.arange(-20, 21)).astype(np.float32), np.float32(0)),
+        np.array([0.0, -0.0, -1.0, np.inf, -np.inf, np.nan, 1e-45], dtype=np.float32)])
+    n = len(fp)
+    rec = records(n, px=rng.uniform(-3, 3, n), py=rng.uniform(-3, 3, n), pz=rng.uniform(-3, 3, n),
+                  footprint=fp)
+    for e_min, max_level in ((-5, 15), (0, 3), (-9, 7)):
+        cfg = dict(kappa=0.5, cam=(0.0, 0.0, -4.0), e_min=e_min, max_level=max_level, log2_slots=12)
+        want, _ = _oracle(cfg).keys(rec)
+        got = _table(psf, cfg).keys(to_device(rec)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, want), (e_min, max_level)
+
+
+@pytest.mark.parametrize("name,insert_mode,fused", MODES[:3])
+def test_footprint_levels_whole_iterations(psf, torch_cuda, name, insert_mode, fused):
+    from synth import workloads as W
+    wl = W.tiny(alpha_mode=0)
+    sc = W.make_scene(wl)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    for it in range(4):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        rec["footprint"] = W.footprints(rec, wl, spread=1.5)
+        d = to_device(rec)
+        orc.insert(rec)
+        orc.update()
+        if fused:
+            out, found = t.iterate(d)
+        else:
+            t.insert(d)
+            t.update()
+            out, found = t.query(d)
+        torch_cuda.cuda.synchronize()
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found), (name, it)
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, (name, it)
+    compare_cells(t.export(), orc.export(), RTOL_F32, name)
+    levels = (t.export()["keys"] >> np.uint64(59)) & np.uint64(15)
+    assert len(np.unique(levels)) > 1
