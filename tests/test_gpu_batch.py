@@ -132,3 +132,33 @@ def test_batch_graph_replay_matches_eager(env):
             assert rel_err(eg["L"], ea["L"]).max() <= RTOL_F32
             assert np.array_equal(ref[i][1].cpu().numpy(), founds[i].cpu().numpy())
             assert rel_err(outs[i].cpu().numpy(), ref[i][0].cpu().numpy()).max() <= RTOL_F32
+
+
+def test_batch_with_footprint_sessions(env):
+    """Sessions whose records carry footprints (their own level rule) mixed
+    with sessions that use the camera distance: each equals the oracle."""
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    ss = _sessions(4)
+    tables = [psf.Table(**wl["table"]) for wl, _ in ss]
+    orcs = [oracle.Oracle(**wl["table"]) for wl, _ in ss]
+    batch = psf.Batch(8)
+    for it in range(2):
+        recs = []
+        for j, (wl, sc) in enumerate(ss):
+            r = dict(_frame(wl, sc, it))
+            if j % 2 == 0:
+                r["footprint"] = W.footprints(r, wl, spread=1.0)
+            recs.append(r)
+        res = batch.iterate(tables, [to_device(r) for r in recs])
+        for o, r in zip(orcs, recs):
+            o.insert(r)
+            o.update()
+    torch.cuda.synchronize()
+    for i in range(len(ss)):
+        compare_cells(tables[i].export(), orcs[i].export(), RTOL_F32, f"session {i}")
+        w_out, w_found = orcs[i].query(recs[i])
+        out, found = res[i]
+        assert np.array_equal(found.cpu().numpy(), w_found)
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32

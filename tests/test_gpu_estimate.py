@@ -125,3 +125,28 @@ def test_invalid_estimate_arguments(env):
     out, applied = psf.estimate(t, t, a, 0, 1.0)  # empty tables: plain estimate, nothing applied
     torch.cuda.synchronize()
     assert int(applied.sum()) == 0 and float(out.abs().sum()) == 0.0
+
+
+def test_estimators_with_footprint_levels(env):
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    wl = W.tiny()
+    sc = W.make_scene(wl)
+    oe_t, fl_t = psf.Table(**wl["table"]), psf.Table(**W.fl_table(wl["table"]))
+    oe_o, fl_o = oracle.Oracle(**wl["table"]), oracle.Oracle(**W.fl_table(wl["table"]))
+    for it in range(2):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        rec["footprint"] = W.footprints(rec, wl, spread=1.5)
+        a, fl = W.estimator_inputs(rec, wl["gen"])
+        a["footprint"] = rec["footprint"]
+        fl = dict(fl, footprint=rec["footprint"])
+        oe_t.iterate(to_device(rec))
+        fl_t.iterate(to_device(fl))
+        oe_o.insert(rec)
+        oe_o.update()
+        fl_o.insert(fl)
+        fl_o.update()
+    _, applied = _check(psf, oracle, oe_t, fl_t, oe_o, fl_o, a, 0, 0.75)
+    assert applied.sum() > 0.5 * applied.numel()
