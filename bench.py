@@ -197,6 +197,33 @@ def form_batched(torch, psf, W, iters=8, sessions=16):
                      "p50_iter_ms": round(float(np.percentile(ms, 50)), 4),
                      "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
                      "dropped": int(sum(t.stats()["dropped"] for t in tabs))}
+        if mode == "batched":
+            # the same batched iteration captured once per frame in a HIP
+            # graph (one context per graph) and replayed
+            ctxs = [psf.Batch(len(wls)) for _ in range(2)]
+            graphs = []
+            gs = torch.cuda.Stream()
+            gs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(gs):
+                for k in range(2):
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=gs):
+                        ctxs[k].iterate(tabs, [f[k] for f in frames], outs=outs, founds=fnds)
+                    graphs.append(g)
+            torch.cuda.current_stream().wait_stream(gs)
+            for k in range(2):
+                graphs[k].replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(iters):
+                graphs[k % 2].replay()
+            torch.cuda.synchronize()
+            gel = time.perf_counter() - t0
+            res["batched_graph_replay"] = {"records_per_s": round(total * iters / gel, 1),
+                                           "ms_per_iter": round(gel / iters * 1e3, 4)}
+            del graphs
+            for c in ctxs:
+                c.close()
         for t in tabs:
             t.close()
         batch.close()
