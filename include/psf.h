@@ -234,6 +234,17 @@ psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const p
 /* Reset (PSF_RESET_* bits). */
 psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream);
 
+/* Local counter reset (Sec. 2.4: besides globally, counters may be zeroed
+ * locally and on demand, where the caller's heuristic detects a change).
+ * Every cell whose box [i*s, (i+1)*s) per axis (s = 2^(e_min + level), i the
+ * cell's grid coordinates as stored, signed 16-bit) meets the closed box
+ * [lo, hi] gets c_old = 0, as PSF_RESET_COUNTERS does for every cell: it is
+ * not reported by queries until blended again, and that blend starts over
+ * with alpha = 1.  Pending samples stay.  lo and hi are host arrays of three
+ * finite floats with lo <= hi; the test is done in binary32 (exact here:
+ * the box corners are integers times powers of two). */
+psf_status psf_reset_region(psf_table* t, const float* lo, const float* hi, psf_stream stream);
+
 /* Keys of n records (all ones for rejected records); test support. */
 psf_status psf_compute_keys(psf_table* t, const psf_records* rec, uint64_t n, uint64_t* d_out_keys,
                             psf_stream stream);

@@ -58,6 +58,7 @@ def _load():
     lib.orc_update.argtypes = [vp]
     lib.orc_query.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
     lib.orc_reset.argtypes = [vp, u32]
+    lib.orc_reset_region.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     lib.orc_count.restype = u64
     lib.orc_count.argtypes = [vp]
     lib.orc_export.restype = u64
@@ -148,6 +149,13 @@ class Oracle:
 
     def reset(self, what: int):
         self._lib.orc_reset(self._h, int(what))
+
+    def reset_region(self, lo, hi):
+        """Zero c_old of every cell whose box meets [lo, hi] (Sec. 2.4, local
+        counter reset)."""
+        a = (ctypes.c_float * 3)(*[float(np.float32(v)) for v in lo])
+        b = (ctypes.c_float * 3)(*[float(np.float32(v)) for v in hi])
+        self._lib.orc_reset_region(self._h, a, b)
 
     def count(self) -> int:
         return int(self._lib.orc_count(self._h))

@@ -359,6 +359,29 @@ void orc_reset(void* h, uint32_t what) {
     for (auto& kv : o->cells) kv.second.c_old = 0;
 }
 
+// Local counter reset (Sec. 2.4: counters zeroed locally, on demand): every
+// cell whose box meets the closed box [lo, hi] gets c_old = 0.  A cell of
+// level l covers [i s, (i + 1) s) per axis, s = 2^(e_min + l), with i its
+// grid coordinate as stored in the key (signed 16-bit); binary32 as the key.
+static bool cell_meets_axis(uint64_t key, int shift, float s, float lo, float hi) {
+  int32_t i = (int32_t)(int16_t)(uint16_t)((key >> shift) & 0xffffu);
+  float a = (float)i * s;
+  float b = (float)(i + 1) * s;
+  return b > lo && a <= hi;
+}
+
+void orc_reset_region(void* h, const float* lo, const float* hi) {
+  Oracle* o = static_cast<Oracle*>(h);
+  for (auto& kv : o->cells) {
+    uint64_t key = kv.first;
+    int lvl = (int)((key >> 59) & 15u);
+    float s = std::ldexp(1.0f, o->cfg.e_min + lvl);
+    if (cell_meets_axis(key, 0, s, lo[0], hi[0]) && cell_meets_axis(key, 16, s, lo[1], hi[1]) &&
+        cell_meets_axis(key, 32, s, lo[2], hi[2]))
+      kv.second.c_old = 0;
+  }
+}
+
 uint64_t orc_count(void* h) { return static_cast<Oracle*>(h)->cells.size(); }
 
 // Cells in ascending key order.  L and s are 3 x cap (SoA).  Returns the

@@ -490,6 +490,18 @@ PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
   return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
 }
 
+PSF_API psf_status psf_reset_region(psf_table* t, const float* lo, const float* hi, psf_stream stream) {
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (!lo || !hi) return fail(PSF_INVALID_ARGUMENT, "region corners are NULL");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]) || lo[c] > hi[c])
+      return fail(PSF_INVALID_ARGUMENT, "region corners must be finite with lo <= hi");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  hipError_t e = psf::launch_reset_region(t->tv, nslots(t), t->cfg.e_min, lo, hi, s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
+}
+
 PSF_API psf_status psf_compute_keys(psf_table* t, const psf_records* rec, uint64_t n,
                                     uint64_t* d_out_keys, psf_stream stream) {
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");

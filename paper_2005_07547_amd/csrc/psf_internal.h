@@ -52,6 +52,9 @@ hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, 
                            int32_t mode, float param, float* out, uint8_t* applied, hipStream_t s);
 hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s);
 hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s);
+// c_old = 0 for every cell whose box meets [lo, hi] (cells at e_min + level).
+hipError_t launch_reset_region(const TableView& tv, uint64_t nslots, int32_t e_min, const float lo[3],
+                               const float hi[3], hipStream_t s);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
 hipError_t launch_count_occupied(const TableView& tv, uint64_t nslots, unsigned long long* out,
                                  hipStream_t s);

@@ -292,6 +292,31 @@ __global__ void k_reset_counters(TableView tv, uint64_t nslots) {
     tv.slots[s].c_old = 0;
 }
 
+// Box of a key's cell along one axis meets [lo, hi]: the cell is
+// [i s, (i + 1) s) with i the signed 16-bit coordinate at bit `shift`.
+__device__ __forceinline__ bool cell_meets(uint64_t key, int32_t shift, float s, float lo, float hi) {
+  const int32_t i = (int32_t)(int16_t)(uint16_t)((key >> shift) & 0xffffu);
+  const float a = (float)i * s, b = (float)(i + 1) * s;
+  return b > lo && a <= hi;
+}
+
+struct Box3 {
+  float lo[3], hi[3];
+};
+
+__global__ void k_reset_region(TableView tv, uint64_t nslots, int32_t e_min, Box3 box) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = tv.keys[s];
+    if (key == kEmpty) continue;
+    const int32_t lvl = (int32_t)((key >> 59) & 15u);
+    const float w = ldexpf(1.0f, e_min + lvl);
+    if (cell_meets(key, 0, w, box.lo[0], box.hi[0]) && cell_meets(key, 16, w, box.lo[1], box.hi[1]) &&
+        cell_meets(key, 32, w, box.lo[2], box.hi[2]))
+      tv.slots[s].c_old = 0;
+  }
+}
+
 __global__ void k_zero_words(uint32_t* p, uint64_t words) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -387,6 +412,17 @@ hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s) {
 
 hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s) {
   k_reset_counters<<<stride_grid(nslots, 256, 8192), 256, 0, s>>>(tv, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_region(const TableView& tv, uint64_t nslots, int32_t e_min, const float lo[3],
+                               const float hi[3], hipStream_t s) {
+  Box3 b;
+  for (int c = 0; c < 3; ++c) {
+    b.lo[c] = lo[c];
+    b.hi[c] = hi[c];
+  }
+  k_reset_region<<<stride_grid(nslots, 256, 8192), 256, 0, s>>>(tv, nslots, e_min, b);
   return hipGetLastError();
 }
 

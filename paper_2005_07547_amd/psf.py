@@ -93,6 +93,7 @@ EXPORTS = [
     ("psf_query", ctypes.c_int, [_vp, _P(psf_queries), _u64, _vp, _vp, _vp]),
     ("psf_iterate", ctypes.c_int, [_vp, _P(psf_records), _u64, _P(psf_queries), _u64, _vp, _vp, _vp]),
     ("psf_reset", ctypes.c_int, [_vp, _u32, _vp]),
+    ("psf_reset_region", ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_float), _vp]),
     ("psf_compute_keys", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp, _vp]),
     ("psf_get_stats", ctypes.c_int, [_vp, _P(psf_stats), _vp]),
     ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
@@ -251,6 +252,12 @@ class Table:
                                      ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_ptr(found)),
                                      current_stream()))
         return out, found
+
+    def reset_region(self, lo, hi):
+        """psf_reset_region: zero c_old of every cell meeting the box [lo, hi]."""
+        a = (ctypes.c_float * 3)(*[float(v) for v in lo])
+        b = (ctypes.c_float * 3)(*[float(v) for v in hi])
+        _check(self._lib.psf_reset_region(self.handle, a, b, current_stream()))
 
     def keys(self, rec: dict):
         import torch

@@ -517,3 +517,38 @@ def test_footprint_levels_whole_iterations(psf, torch_cuda, name, insert_mode, f
     compare_cells(t.export(), orc.export(), RTOL_F32, name)
     levels = (t.export()["keys"] >> np.uint64(59)) & np.uint64(15)
     assert len(np.unique(levels)) > 1
+
+
+# ----------------------------------------------------------------- local counter reset
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_local_counter_reset(psf, torch_cuda, insert_mode):
+    from synth import workloads as W
+    wl = W.tiny(alpha_mode=0)
+    sc = W.make_scene(wl)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"], insert_mode=insert_mode)
+    regions = [((0.2, -0.1, 0.3), (0.6, 0.45, 0.9)), ((-5, -5, -5), (0.5, 5, 5)), ((0.25, 0.25, 0.25), (0.25, 0.25, 0.25))]
+    for it in range(5):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        d = to_device(rec)
+        orc.insert(rec)
+        orc.update()
+        out, found = t.iterate(d)
+        if it < len(regions):
+            before = int(found.sum())
+            lo, hi = regions[it]
+            orc.reset_region(lo, hi)
+            t.reset_region(lo, hi)
+            out, found = t.query(d)
+            if it < 2:  # these regions hold cells: some vertices lose their answer
+                assert 0 < int(found.sum()) < before, it
+        torch_cuda.cuda.synchronize()
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found), it
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, it
+        compare_cells(t.export(), orc.export(), RTOL_F32, f"after frame {it}")
+    with pytest.raises(psf.PsfError):
+        t.reset_region((1, 0, 0), (0, 1, 1))
+    with pytest.raises(psf.PsfError):
+        t.reset_region((0, 0, 0), (float("nan"), 1, 1))

@@ -527,3 +527,46 @@ def test_filter_tracks_subset_identically():
     j = np.searchsorted(ef["keys"], pick)
     assert np.array_equal(es["c_old"], ef["c_old"][j])
     assert np.array_equal(es["L"], ef["L"][:, j])
+
+
+def test_local_counter_reset_worked_example():
+    """Sec. 2.4: counters may be zeroed locally.  Level-0 cells of edge 1
+    (e_min 0, fixed level); the region [0.9, 2] x [0, 1] x [0, 1] meets the
+    cells [0,1) and [2,3) along x (closed upper bound) but not [-1,0).  Reset
+    cells are hidden from queries until blended again, and that blend starts
+    over (alpha = 1: the new mean)."""
+    orc = oracle.Oracle(kappa=0.0, e_min=0, alpha_mode=oracle.ALPHA_CONST, alpha=0.25)
+    xs = [0.5, 2.5, -0.5]
+    rec = records(3, px=xs, py=0.5, pz=0.5, r=[1.0, 2.0, 3.0], g=[1.0, 2.0, 3.0], b=[1.0, 2.0, 3.0])
+    orc.insert(rec)
+    orc.update()
+    orc.reset_region((0.9, 0.0, 0.0), (2.0, 1.0, 1.0))
+    _, found = orc.query(rec)
+    assert list(found) == [0, 0, 1]
+    ex = orc.export()
+    assert sorted(ex["c_old"].tolist()) == [0, 0, 1]
+    rec2 = records(3, px=xs, py=0.5, pz=0.5, r=[5.0, 6.0, 7.0], g=[5.0, 6.0, 7.0], b=[5.0, 6.0, 7.0])
+    orc.insert(rec2)
+    orc.update()
+    out, found = orc.query(rec2)
+    assert list(found) == [1, 1, 1]
+    # reset cells take the new mean; the kept one blends 3/4 * 3 + 1/4 * 7
+    assert list(out[0]) == [5.0, 6.0, 4.0]
+
+
+def test_local_counter_reset_whole_space_equals_global_reset():
+    from synth import workloads as W
+    wl = W.tiny()
+    sc = W.make_scene(wl)
+    a, b = oracle.Oracle(**wl["table"]), oracle.Oracle(**wl["table"])
+    for it in range(2):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        for o in (a, b):
+            o.insert(rec)
+            o.update()
+    a.reset(oracle.RESET_COUNTERS)
+    b.reset_region((-1e30, -1e30, -1e30), (1e30, 1e30, 1e30))
+    ea, eb = a.export(), b.export()
+    assert np.array_equal(ea["keys"], eb["keys"]) and np.array_equal(ea["c_old"], eb["c_old"])
+    assert int(eb["c_old"].sum()) == 0
