@@ -284,6 +284,43 @@ def form_estimate(torch, psf, W, iters=32, warm_frames=4):
     return res
 
 
+def form_progressive(torch, psf, W, iters=16, paths=921600, verts=4):
+    """The progressive solver's feedback loop (Sec. 2.2) in the closed
+    furnace: every frame looks up the previous approximant at each path's
+    next vertex, forms L_e + L~ * f G w / p and inserts and blends it."""
+    import numpy as np
+    cfg = dict(W.furnace_table(log2_slots=20), flags=psf.PSF_FLAG_TIMING)
+    n = paths * verts
+    t = psf.Table(**dict(cfg, max_batch=n))
+    frames = []
+    for it in range(2):
+        x, nx, tp, em = W.furnace_paths(paths, verts, it)
+        frames.append((_dev(x, torch), _dev(nx, torch),
+                       tuple(torch.from_numpy(a).cuda() for a in tp), tuple(torch.from_numpy(a).cuda() for a in em)))
+    out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    for k in range(4):
+        f = frames[k % 2]
+        t.progressive_step(f[0], f[1], f[2], f[3], out=out)
+    torch.cuda.synchronize()
+    t.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for k in range(iters):
+        f = frames[k % 2]
+        t.progressive_step(f[0], f[1], f[2], f[3], out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: round(v[1] / max(1, v[0]), 5) for k, v in t.kernel_times().items()}
+    L = t.export()["L"]
+    le, rho = np.array([1.0, 0.5, 0.25]), np.array([0.5, 0.6, 0.7])
+    rel = np.abs(L / (le / (1.0 - rho))[:, None] - 1.0)
+    res = {"scene": "closed furnace (unit sphere, L_e (1, 0.5, 0.25), albedo (0.5, 0.6, 0.7))",
+           "paths": paths, "vertices_per_path": verts, "records_per_s": round(n * iters / el, 1),
+           "ms_per_frame": round(el / iters * 1e3, 4), "kernels_avg_ms": kt,
+           "mean_rel_error_to_closed_form": round(float(rel.mean()), 6), "frames_run": iters + 4}
+    t.close()
+    return res
+
+
 def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     """Poisson arrivals at 20/s, resolutions lognormal around 720p, 32-128
     iterations each, 1 spp, 4 vertices; continuous batching under an HBM
@@ -356,8 +393,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
-    ap.add_argument("--forms", default="precision,batched,serving,estimate",
-                    help="comma list of extra forms to measure (precision,batched,serving,estimate) or ''")
+    ap.add_argument("--forms", default="precision,batched,serving,estimate,progressive",
+                    help="comma list of extra forms to measure (precision,batched,serving,estimate,"
+                         "progressive) or ''")
     ap.add_argument("--untuned", action="store_true",
                     help="library default launch parameters instead of the recorded tuned ones")
     ap.add_argument("--copy-calib", action="store_true",
@@ -511,7 +549,7 @@ def main():
     forms = {}
     for name in [f for f in args.forms.split(",") if f]:
         fn = {"precision": form_precision, "batched": form_batched, "serving": form_serving,
-              "estimate": form_estimate}[name]
+              "estimate": form_estimate, "progressive": form_progressive}[name]
         print(f"# measuring form {name}", file=sys.stderr, flush=True)
         forms[name] = fn(torch, psf, W)
         torch.cuda.empty_cache()

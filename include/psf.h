@@ -101,7 +101,8 @@ enum {
   PSF_K_BATCH = 7,
   PSF_K_TRANSPOSE = 8,
   PSF_K_ESTIMATE = 9,
-  PSF_K_COUNT = 10
+  PSF_K_STEP = 10,
+  PSF_K_COUNT = 11
 };
 
 /*
@@ -230,6 +231,28 @@ psf_status psf_query(psf_table* t, const psf_queries* q, uint64_t n, float* d_ou
  * record its cell's new value, so the query costs no second lookup. */
 psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const psf_queries* q,
                        uint64_t nq, float* d_out_rgb, uint8_t* d_out_found, psf_stream stream);
+
+/* One step of the progressive solver (Sec. 2.2, Eq. 8-9; Algorithm 1): at
+ * each of n path vertices x_i the new sample is
+ *
+ *   Lbar_i = L_e(x_i) + L~(x_{i+1}) * t_i
+ *
+ * where L~(x_{i+1}) is the approximant at the path's next vertex as
+ * psf_query returns it (the state of the last completed update: the
+ * previous frame's approximant; 0 where the next vertex has no blended cell
+ * or no valid key, e.g. a path that ended) and t_i = f G w / p is the
+ * caller's throughput factor of the sampled step x_i -> x_{i+1}.  The
+ * samples are written to d_samples (3*n floats, SoA, caller-owned device
+ * memory), inserted at the vertices x and blended, as psf_iterate with no
+ * queries would.  x->r, g, b are ignored; le may be NULL (no emission). */
+typedef struct psf_step_args {
+  const float *le_r, *le_g, *le_b;  /* emission at x_i (all three or none) */
+  const float *t_r, *t_g, *t_b;     /* throughput factor f G w / p */
+} psf_step_args;
+
+psf_status psf_progressive_step(psf_table* t, const psf_records* x, const psf_queries* next,
+                                const psf_step_args* a, uint64_t n, float* d_samples,
+                                psf_stream stream);
 
 /* Reset (PSF_RESET_* bits). */
 psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream);

@@ -226,3 +226,24 @@ def estimate(orc_oe: Oracle, orc_fli: Oracle, a: dict, mode: int, param: float):
     both = (fo != 0) & (fi != 0)
     e = np.where(both[None, :], e, w * g)
     return e, both.astype(np.uint8)
+
+
+# --------------------------------------------------------------------------
+# Progressive solver (Sec. 2.2, Eq. 8-9; Algorithm 1).
+def progressive_step(orc: Oracle, x: dict, nxt: dict, tput, le=None):
+    """One frame of the progressive solver: the sample at each vertex x_i is
+    L_e(x_i) + L~(x_{i+1}) t_i, with L~ the approximant at the path's next
+    vertex as the last completed blend left it (0 where it has no blended
+    cell) and t_i = f G w / p of the sampled step; the samples are projected
+    onto the cells at x (Eq. 8, as insert) and blended (Eq. 10-11).  The
+    samples are formed in binary64 and handed to the insert as binary32
+    records, as a caller's renderer would.  Returns the samples (3, n)."""
+    L, _ = orc.query(nxt)
+    t = np.stack([np.asarray(v, dtype=np.float64) for v in tput])
+    e = np.zeros_like(t) if le is None else np.stack([np.asarray(v, dtype=np.float64) for v in le])
+    lbar = e + L * t
+    rec = {k: v for k, v in x.items() if k not in ("r", "g", "b")}
+    rec["r"], rec["g"], rec["b"] = (lbar[c].astype(np.float32) for c in range(3))
+    orc.insert(rec)
+    orc.update()
+    return lbar

@@ -490,6 +490,35 @@ PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
   return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
 }
 
+PSF_API psf_status psf_progressive_step(psf_table* t, const psf_records* x, const psf_queries* next,
+                                        const psf_step_args* a, uint64_t n, float* d_samples,
+                                        psf_stream stream) {
+  std::string why;
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!x || !x->px || !x->py || !x->pz || !x->nx || !x->ny || !x->nz)
+    return fail(PSF_INVALID_ARGUMENT, "vertex position and normal arrays are required");
+  if (x->rough && (!x->ox || !x->oy || !x->oz))
+    return fail(PSF_INVALID_ARGUMENT, "direction arrays are required when roughness is given");
+  if (!qry_ok(next, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (!a || !a->t_r || !a->t_g || !a->t_b) return fail(PSF_INVALID_ARGUMENT, "throughput arrays are required");
+  if ((a->le_r != nullptr) != (a->le_g != nullptr) || (a->le_r != nullptr) != (a->le_b != nullptr))
+    return fail(PSF_INVALID_ARGUMENT, "emission arrays: all three or none");
+  if (!d_samples) return fail(PSF_INVALID_ARGUMENT, "sample array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  psf::StepPtrs sp{qry_ptrs(next), a->le_r, a->le_g, a->le_b, a->t_r, a->t_g, a->t_b};
+  hipError_t e = timed(t, PSF_K_STEP, s, [&] {
+    return psf::launch_step_samples(sp, n, t->kp, t->tv, t->cfg.state_dtype, d_samples, s);
+  });
+  if (e != hipSuccess) return hip_fail(e, "progressive step launch");
+  psf_records r = *x;
+  r.r = d_samples;
+  r.g = d_samples + n;
+  r.b = d_samples + 2 * n;
+  return psf_iterate(t, &r, n, nullptr, 0, nullptr, nullptr, stream);
+}
+
 PSF_API psf_status psf_reset_region(psf_table* t, const float* lo, const float* hi, psf_stream stream) {
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
   if (!lo || !hi) return fail(PSF_INVALID_ARGUMENT, "region corners are NULL");
@@ -783,7 +812,7 @@ PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* to
 
 PSF_API const char* psf_kernel_name(uint32_t k) {
   static const char* names[PSF_K_COUNT] = {"keys", "insert_direct", "bin", "merge", "merge_blend",
-                                           "update", "query", "batch", "transpose", "estimate"};
+                                           "update", "query", "batch", "transpose", "estimate", "step"};
   return k < PSF_K_COUNT ? names[k] : "";
 }
 

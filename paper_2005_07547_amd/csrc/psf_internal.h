@@ -50,6 +50,14 @@ struct EstPtrs {
 hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, const TableView& tv_o,
                            int32_t dt_o, const KeyParams& kp_i, const TableView& tv_i, int32_t dt_i,
                            int32_t mode, float param, float* out, uint8_t* applied, hipStream_t s);
+// Progressive-solver samples: out = le + L~(next) * t per channel (le may be
+// null pointers).
+struct StepPtrs {
+  QryPtrs next;
+  const float *le_r, *le_g, *le_b, *t_r, *t_g, *t_b;
+};
+hipError_t launch_step_samples(const StepPtrs& a, uint64_t n, const KeyParams& kp, const TableView& tv,
+                               int32_t dtype, float* out, hipStream_t s);
 hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s);
 hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s);
 // c_old = 0 for every cell whose box meets [lo, hi] (cells at e_min + level).

@@ -271,6 +271,22 @@ __global__ void __launch_bounds__(kEstThreads) k_estimate(EstPtrs a, uint64_t n,
   }
 }
 
+// ------------------------------------------------------------------ progressive solver
+// Sec. 2.2, Eq. 9: the new sample at x_i transports the current approximant
+// at the next vertex once: Lbar = L_e + L~(x_{i+1}) * f G w / p.
+__global__ void __launch_bounds__(256) k_step_samples(StepPtrs a, uint64_t n, KeyParams kp, TableView tv,
+                                                      int32_t dtype, float* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float L[3];
+  lookup_key(tv, dtype, query_key(kp, a.next, i), L);
+  const bool le = a.le_r != nullptr;
+  const float e[3] = {le ? a.le_r[i] : 0.0f, le ? a.le_g[i] : 0.0f, le ? a.le_b[i] : 0.0f};
+  const float t[3] = {a.t_r[i], a.t_g[i], a.t_b[i]};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[(uint64_t)c * n + i] = e[c] + L[c] * t[c];
+}
+
 // ------------------------------------------------------------------ reset / init
 __global__ void k_clear(TableView tv, uint64_t nslots) {
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
@@ -402,6 +418,13 @@ hipError_t launch_estimate(const EstPtrs& a, uint64_t n, const KeyParams& kp_o, 
   if (n == 0) return hipSuccess;
   k_estimate<<<grid_for(n, kEstThreads * kEstPerThread), kEstThreads, 0, s>>>(a, n, kp_o, tv_o, dt_o, kp_i, tv_i,
                                                                              dt_i, mode, param, out, applied);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_samples(const StepPtrs& a, uint64_t n, const KeyParams& kp, const TableView& tv,
+                               int32_t dtype, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_step_samples<<<grid_for(n, 256), 256, 0, s>>>(a, n, kp, tv, dtype, out);
   return hipGetLastError();
 }
 

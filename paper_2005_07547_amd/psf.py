@@ -23,7 +23,7 @@ PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
 PSF_FLAG_PROBE_STATS = 1
 PSF_FLAG_TIMING = 2
 PSF_FLAG_TRANSPOSE_RUNS = 4
-PSF_K_COUNT = 10
+PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 
 REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
@@ -63,6 +63,10 @@ class psf_estimate_args(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in EST_FIELDS]
 
 
+class psf_step_args(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("le_r", "le_g", "le_b", "t_r", "t_g", "t_b")]
+
+
 class psf_stats(ctypes.Structure):
     _fields_ = [
         ("submitted", ctypes.c_uint64), ("skipped", ctypes.c_uint64), ("dropped", ctypes.c_uint64),
@@ -92,6 +96,8 @@ EXPORTS = [
     ("psf_temporal_update", ctypes.c_int, [_vp, _vp]),
     ("psf_query", ctypes.c_int, [_vp, _P(psf_queries), _u64, _vp, _vp, _vp]),
     ("psf_iterate", ctypes.c_int, [_vp, _P(psf_records), _u64, _P(psf_queries), _u64, _vp, _vp, _vp]),
+    ("psf_progressive_step", ctypes.c_int, [_vp, _P(psf_records), _P(psf_queries), _P(psf_step_args), _u64,
+                                            _vp, _vp]),
     ("psf_reset", ctypes.c_int, [_vp, _u32, _vp]),
     ("psf_reset_region", ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_float), _vp]),
     ("psf_compute_keys", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp, _vp]),
@@ -252,6 +258,27 @@ class Table:
                                      ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_ptr(found)),
                                      current_stream()))
         return out, found
+
+    def progressive_step(self, x: dict, nxt: dict, tput, le=None, out=None):
+        """psf_progressive_step: samples L_e + L~(next) * tput at the vertices
+        x (their r, g, b are not used), inserted and blended.  tput and le are
+        sequences of three device arrays (le None: no emission).  Returns the
+        samples (3, n)."""
+        import torch
+        n = int(x["px"].numel())
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        xs = make_records({k: v for k, v in x.items() if k not in ("r", "g", "b")})
+        qs = make_queries(nxt)
+        a = psf_step_args()
+        for f, v in zip(("t_r", "t_g", "t_b"), tput):
+            setattr(a, f, _ptr(_device_f32(v, f)))
+        if le is not None:
+            for f, v in zip(("le_r", "le_g", "le_b"), le):
+                setattr(a, f, _ptr(_device_f32(v, f)))
+        _check(self._lib.psf_progressive_step(self.handle, ctypes.byref(xs), ctypes.byref(qs), ctypes.byref(a), n,
+                                              ctypes.c_void_p(_ptr(out)), current_stream()))
+        return out
 
     def reset_region(self, lo, hi):
         """psf_reset_region: zero c_old of every cell meeting the box [lo, hi]."""

@@ -182,3 +182,64 @@ def footprints(rec: dict, wl: dict, spread: float = 1.0) -> np.ndarray:
     k = np.arange(d.shape[0], dtype=np.float64)
     u = (np.mod(k * 0.7548776662466927, 1.0) * 2.0 - 1.0) * spread
     return (k_s * theta * d * np.exp2(u)).astype(np.float32)
+
+
+def furnace_paths(n_paths: int, verts: int, it: int, seed: int = 9, le=(1.0, 0.5, 0.25),
+                  albedo=(0.5, 0.6, 0.7)):
+    """Paths inside a closed furnace: the unit sphere at the origin, seen from
+    its centre, emitting le everywhere and reflecting diffusely with the
+    given albedo.  Each path leaves the centre in a uniformly drawn direction
+    and bounces `verts` times with cosine-weighted directions, so the
+    throughput factor f G w / p of every step is the albedo.  Returns (x,
+    nxt, tput, le): the vertices 1..verts as records without values
+    (depth-major), the vertices 2..verts+1 as queries, and the per-vertex
+    throughput and emission arrays (three each).  Seeded by (seed, it)."""
+    rng = np.random.default_rng([seed, it])
+    f32 = np.float32
+    d = rng.normal(size=(3, n_paths))
+    d /= np.linalg.norm(d, axis=0)
+    pos = [d.copy()]          # first hit: the sphere point along d from the centre
+    wo = [-d]                 # back toward the centre
+    cur = d.copy()
+    for _ in range(verts):
+        nrm = -cur                               # inward normal
+        u1, u2 = rng.uniform(size=(2, n_paths))
+        r, phi = np.sqrt(u1), 2.0 * np.pi * u2
+        lx, ly, lz = r * np.cos(phi), r * np.sin(phi), np.sqrt(np.maximum(0.0, 1.0 - u1))
+        # orthonormal frame around the normal (Duff et al. 2017)
+        sgn = np.where(nrm[2] >= 0.0, 1.0, -1.0)
+        a = -1.0 / (sgn + nrm[2])
+        b = nrm[0] * nrm[1] * a
+        t1 = np.stack([1.0 + sgn * nrm[0] * nrm[0] * a, sgn * b, -sgn * nrm[0]])
+        t2 = np.stack([b, sgn + nrm[1] * nrm[1] * a, -nrm[1]])
+        w = lx * t1 + ly * t2 + lz * nrm
+        w /= np.linalg.norm(w, axis=0)
+        tt = -2.0 * np.sum(cur * w, axis=0)      # second intersection with |p| = 1
+        nxt = cur + tt * w
+        nxt /= np.linalg.norm(nxt, axis=0)
+        pos.append(nxt)
+        wo.append(-w)
+        cur = nxt
+    P = np.stack(pos)        # (verts + 1, 3, n)
+    W = np.stack(wo)
+
+    def pack(sl, with_dir):
+        p = P[sl].transpose(1, 0, 2).reshape(3, -1)
+        o = W[sl].transpose(1, 0, 2).reshape(3, -1)
+        n = -p
+        out = {"px": p[0], "py": p[1], "pz": p[2], "nx": n[0], "ny": n[1], "nz": n[2]}
+        if with_dir:
+            out.update(ox=o[0], oy=o[1], oz=o[2])
+        return {k: np.ascontiguousarray(v, dtype=f32) for k, v in out.items()}
+
+    x = pack(slice(0, verts), True)
+    nx = pack(slice(1, verts + 1), True)
+    m = n_paths * verts
+    tput = tuple(np.full(m, c, dtype=f32) for c in albedo)
+    emit = tuple(np.full(m, c, dtype=f32) for c in le)
+    return x, nx, tput, emit
+
+
+def furnace_table(log2_slots: int = 16) -> dict:
+    """Fixed-level table for the furnace (edge 1/8, 4 x 4 normal bins)."""
+    return _table(log2_slots, (0.0, 0.0, 0.0), 60.0, 64, 1.0, -3) | {"kappa": 0.0}

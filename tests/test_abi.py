@@ -59,7 +59,8 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no host C compiler")
     structs = {"psf_config": psf.psf_config, "psf_records": psf.psf_records,
                "psf_queries": psf.psf_queries, "psf_stats": psf.psf_stats,
-               "psf_session": psf.psf_session, "psf_estimate_args": psf.psf_estimate_args}
+               "psf_session": psf.psf_session, "psf_estimate_args": psf.psf_estimate_args,
+               "psf_step_args": psf.psf_step_args}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psf.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
