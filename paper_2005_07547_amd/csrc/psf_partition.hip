@@ -9,14 +9,20 @@
 //   bin   -- one block per tile of records computes the keys, counts records
 //            per partition in LDS, sorts the tile by partition in LDS and
 //            writes it out coalesced (keys, then rgb triples) to a staging
-//            area, plus the tile's exclusive per-partition offsets;
+//            area, plus the tile's exclusive per-partition offsets (and,
+//            for the fused query, each record's position in the tile);
+//   (transpose -- for large launches, the offset table turned so that a
+//            partition's offsets are one row);
 //   merge -- one block per partition loads the partition's keys into LDS,
 //            gathers that partition's entries from every tile, finds or
-//            claims each key's slot and accumulates count and sums with LDS
-//            atomics, then writes the partition back: either adding into the
-//            global accumulators (plain insert) or, when the whole frame is in
-//            this launch, applying the temporal blend (Eq. 10-11) directly so
-//            the accumulators never touch HBM.
+//            claims each key's slot and accumulates count (u32) and sums
+//            (binary64) with LDS atomics, then writes the partition back:
+//            either adding into the global accumulators (plain insert) or,
+//            when the whole frame is in this launch, applying the temporal
+//            blend (Eq. 10-11) directly so the accumulators never touch HBM;
+//            when the frame's queries are its records, it then writes each
+//            staged entry's new cell value over the entry;
+//   unstage -- one block per tile returns those values in record order.
 //
 // A partition is owned by exactly one block in the merge pass, so the
 // write-back uses plain loads and stores.
