@@ -224,6 +224,16 @@ psf_status psf_temporal_update(psf_table* t, psf_stream stream);
 psf_status psf_query(psf_table* t, const psf_queries* q, uint64_t n, float* d_out_rgb,
                      uint8_t* d_out_found, psf_stream stream);
 
+/* Multi-level lookup (Sec. 2.3: the finite elements form a hierarchy of
+ * levels).  As psf_query, but a query vertex whose own cell has no blended
+ * value is answered by the finest coarser cell that has one (the same
+ * normal and direction bins at levels l + 1 .. l + levels_up, up to
+ * max_level).  d_out_level (nullable, n bytes) receives 0 where no level
+ * answered, else 1 + the number of levels above the vertex's own.
+ * levels_up <= 15; 0 is psf_query. */
+psf_status psf_query_levels(psf_table* t, const psf_queries* q, uint64_t n, uint32_t levels_up,
+                            float* d_out_rgb, uint8_t* d_out_level, psf_stream stream);
+
 /* One whole iteration: insert rec, temporal update, then query q.  Same
  * result as the three calls in sequence; when the table has no pending
  * inserts the partitioned strategy fuses insert and blend in one pass, and

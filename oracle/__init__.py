@@ -58,6 +58,7 @@ def _load():
     lib.orc_update.argtypes = [vp]
     lib.orc_query.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
     lib.orc_reset.argtypes = [vp, u32]
+    lib.orc_query_levels.argtypes = [vp, ctypes.POINTER(_Records), u64, ctypes.c_int, vp, vp]
     lib.orc_reset_region.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     lib.orc_count.restype = u64
     lib.orc_count.argtypes = [vp]
@@ -146,6 +147,16 @@ class Oracle:
         found = np.zeros(n, dtype=np.uint8)
         self._lib.orc_query(self._h, ctypes.byref(p.s), n, out.ctypes.data, found.ctypes.data)
         return out, found
+
+    def query_levels(self, rec, up: int):
+        """Lookup falling back to up to `up` coarser levels (Sec. 2.3);
+        returns (rgb (3, n), level (n,): 0 none, else 1 + levels above)."""
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        out = np.zeros((3, n), dtype=np.float64)
+        lv = np.zeros(n, dtype=np.uint8)
+        self._lib.orc_query_levels(self._h, ctypes.byref(p.s), n, int(up), out.ctypes.data, lv.ctypes.data)
+        return out, lv
 
     def reset(self, what: int):
         self._lib.orc_reset(self._h, int(what))

@@ -175,9 +175,10 @@ struct KeyResult {
 };
 
 // rough may be null (all vertices diffuse); fp may be null (level from the
-// camera distance), else it must be finite and positive.
+// camera distance), else it must be finite and positive.  up > 0 gives the
+// key of the cell that many levels coarser (invalid past max_level).
 KeyResult key_of(const Config& c, float px, float py, float pz, float nx, float ny, float nz,
-                 float ox, float oy, float oz, const float* rough, const float* fp) {
+                 float ox, float oy, float oz, const float* rough, const float* fp, int up = 0) {
   KeyResult r{false, false, 0};
   if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return r;
   if (fp && !(std::isfinite(*fp) && *fp > 0.0f)) return r;
@@ -187,7 +188,8 @@ KeyResult key_of(const Config& c, float px, float py, float pz, float nx, float 
     glossy = (*rough < c.rough_thr);
     if (glossy && !finite3(ox, oy, oz)) return r;
   }
-  int lvl = fp ? level_of_footprint(c, *fp) : level_of(c, px, py, pz);
+  int lvl = (fp ? level_of_footprint(c, *fp) : level_of(c, px, py, pz)) + up;
+  if (lvl > c.max_level) return r;
   int shift = c.e_min + lvl;
   bool ovf = false;
   int64_t ix = grid_coord(px, shift, &ovf);
@@ -255,11 +257,11 @@ void* orc_create(const float* cam, float kappa, int e_min, int max_level, int no
 
 void orc_destroy(void* h) { delete static_cast<Oracle*>(h); }
 
-static KeyResult key_at(const Config& c, const orc_records* r, uint64_t i) {
+static KeyResult key_at(const Config& c, const orc_records* r, uint64_t i, int up = 0) {
   const float* const* f = r->f;
   float ox = f[6] ? f[6][i] : 0.0f, oy = f[7] ? f[7][i] : 0.0f, oz = f[8] ? f[8][i] : 0.0f;
   return key_of(c, f[0][i], f[1][i], f[2][i], f[3][i], f[4][i], f[5][i], ox, oy, oz,
-                f[12] ? &f[12][i] : nullptr, f[13] ? &f[13][i] : nullptr);
+                f[12] ? &f[12][i] : nullptr, f[13] ? &f[13][i] : nullptr, up);
 }
 
 // Keys of n records; invalid (skipped) records get all-ones.  overflow[i]
@@ -349,6 +351,31 @@ void orc_query(void* h, const orc_records* r, uint64_t n, double* out_rgb, uint8
 
 // what bit 0: zero c_old of every cell (global counter reset, Sec. 2.4);
 // bit 1: remove every cell.
+// Multi-level lookup (Sec. 2.3, a hierarchy of levels): the vertex's own
+// cell if blended, else the finest blended cell up to `up` levels coarser.
+// level[i] = 0 if none answered, else 1 + levels above the vertex's own.
+void orc_query_levels(void* h, const orc_records* r, uint64_t n, int up, double* out_rgb, uint8_t* level) {
+  Oracle* o = static_cast<Oracle*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    double v[3] = {0.0, 0.0, 0.0};
+    uint8_t lv = 0;
+    for (int k = 0; k <= up; ++k) {
+      KeyResult kr = key_at(o->cfg, r, i, k);
+      if (!kr.valid) break;
+      auto it = o->cells.find(kr.key);
+      if (it != o->cells.end() && it->second.c_old > 0) {
+        for (int ch = 0; ch < 3; ++ch) v[ch] = it->second.L[ch];
+        lv = (uint8_t)(k + 1);
+        break;
+      }
+    }
+    out_rgb[i] = v[0];
+    out_rgb[n + i] = v[1];
+    out_rgb[2 * n + i] = v[2];
+    if (level) level[i] = lv;
+  }
+}
+
 void orc_reset(void* h, uint32_t what) {
   Oracle* o = static_cast<Oracle*>(h);
   if (what & 2u) {

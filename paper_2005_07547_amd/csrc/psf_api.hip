@@ -490,6 +490,23 @@ PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
   return e == hipSuccess ? PSF_OK : hip_fail(e, "reset launch");
 }
 
+PSF_API psf_status psf_query_levels(psf_table* t, const psf_queries* q, uint64_t n, uint32_t levels_up,
+                                    float* d_out_rgb, uint8_t* d_out_level, psf_stream stream) {
+  std::string why;
+  if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (n == 0) return PSF_OK;
+  if (!qry_ok(q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (!d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
+  if (levels_up > 15) return fail(PSF_INVALID_ARGUMENT, "levels_up must be <= 15");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  hipError_t e = timed(t, PSF_K_QUERY, s, [&] {
+    return psf::launch_query_hier(qry_ptrs(q), n, levels_up, t->kp, t->tv, t->cfg.state_dtype, d_out_rgb,
+                                  d_out_level, s);
+  });
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
+}
+
 PSF_API psf_status psf_progressive_step(psf_table* t, const psf_records* x, const psf_queries* next,
                                         const psf_step_args* a, uint64_t n, float* d_samples,
                                         psf_stream stream) {

@@ -177,11 +177,12 @@ __device__ __forceinline__ uint32_t octa_bin(float x, float y, float z, int32_t 
 // has_rough is false when the caller supplied no roughness array (every
 // vertex diffuse); the direction is read only for glossy vertices.  With a
 // footprint (has_fp) the level comes from it (it must be finite and > 0),
-// else from the camera distance.
+// else from the camera distance.  up > 0 asks for the cell that many levels
+// coarser (false if that passes max_level).
 __device__ __forceinline__ bool cell_key(const KeyParams& kp, float px, float py, float pz, float nx,
                                          float ny, float nz, float ox, float oy, float oz,
                                          bool has_rough, float rough, bool has_fp, float fp,
-                                         uint64_t& key, bool& ovf) {
+                                         uint64_t& key, bool& ovf, int32_t up = 0) {
   if (!finite3(px, py, pz) || !finite3(nx, ny, nz)) return false;
   if (has_fp && !(__builtin_isfinite(fp) && fp > 0.0f)) return false;
   bool glossy = false;
@@ -190,7 +191,8 @@ __device__ __forceinline__ bool cell_key(const KeyParams& kp, float px, float py
     glossy = rough < kp.rough_thr;
     if (glossy && !finite3(ox, oy, oz)) return false;
   }
-  const int32_t lvl = has_fp ? footprint_level(kp, fp) : cell_level(kp, px, py, pz);
+  const int32_t lvl = (has_fp ? footprint_level(kp, fp) : cell_level(kp, px, py, pz)) + up;
+  if (lvl > kp.max_level) return false;
   const int32_t shift = kp.e_min + lvl;
   ovf = false;
   const uint64_t ix = grid16(px, shift, ovf);
@@ -318,7 +320,7 @@ __device__ __forceinline__ uint8_t lookup_finish(const TableView& tv, int32_t dt
 
 // Key of query i of a structure-of-arrays query set (kEmpty if rejected).
 template <class Q>
-__device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, uint64_t i) {
+__device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, uint64_t i, int32_t up = 0) {
   const bool hr = q.rough != nullptr;
   const float ro = hr ? q.rough[i] : 0.0f;
   const bool gl = hr && ro < kp.rough_thr;
@@ -326,7 +328,8 @@ __device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, u
   uint64_t key;
   bool ovf;
   if (!cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
-                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, hf, hf ? q.footprint[i] : 0.0f, key, ovf))
+                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, hf, hf ? q.footprint[i] : 0.0f, key, ovf,
+                up))
     return kEmpty;
   return key;
 }

@@ -58,6 +58,11 @@ struct StepPtrs {
 };
 hipError_t launch_step_samples(const StepPtrs& a, uint64_t n, const KeyParams& kp, const TableView& tv,
                                int32_t dtype, float* out, hipStream_t s);
+// Lookup falling back to up to `up` coarser levels; level_out[i] = 0 (no
+// blended cell) or 1 + the number of levels above the query's own.
+hipError_t launch_query_hier(const QryPtrs& q, uint64_t n, uint32_t up, const KeyParams& kp,
+                             const TableView& tv, int32_t dtype, float* out, uint8_t* level_out,
+                             hipStream_t s);
 hipError_t launch_clear(const TableView& tv, uint64_t nslots, hipStream_t s);
 hipError_t launch_reset_counters(const TableView& tv, uint64_t nslots, hipStream_t s);
 // c_old = 0 for every cell whose box meets [lo, hi] (cells at e_min + level).

@@ -219,6 +219,31 @@ __global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams 
   if (found) found[i] = hit;
 }
 
+// ------------------------------------------------------------------ multi-level lookup
+// Sec. 2.3: finite elements come in a hierarchy of levels.  A vertex whose
+// own cell has no blended value is answered by the finest coarser cell
+// (same normal and direction bins) that has one, at most `up` levels up.
+__global__ void __launch_bounds__(256) k_query_hier(QryPtrs q, uint64_t n, uint32_t up, KeyParams kp,
+                                                    TableView tv, int32_t dtype, float* out,
+                                                    uint8_t* level_out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float rgb[3] = {0.0f, 0.0f, 0.0f};
+  uint8_t lv = 0;
+  for (uint32_t k = 0; k <= up; ++k) {
+    const uint64_t key = query_key(kp, q, i, (int32_t)k);
+    if (key == kEmpty) break;  // invalid vertex, or past the coarsest level
+    if (lookup_key(tv, dtype, key, rgb)) {
+      lv = (uint8_t)(k + 1);
+      break;
+    }
+  }
+  out[i] = rgb[0];
+  out[n + i] = rgb[1];
+  out[2 * n + i] = rgb[2];
+  if (level_out) level_out[i] = lv;
+}
+
 // ------------------------------------------------------------------ two-field estimators
 // Sec. 4.2 (Eq. 25) and Sec. 5 (Eq. 28): the control variate h = f~L_i(x,
 // w_i) has the known integral L~o\e(x, w_o).  mode 0: wp (g - beta h) +
@@ -425,6 +450,14 @@ hipError_t launch_step_samples(const StepPtrs& a, uint64_t n, const KeyParams& k
                                int32_t dtype, float* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_step_samples<<<grid_for(n, 256), 256, 0, s>>>(a, n, kp, tv, dtype, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_hier(const QryPtrs& q, uint64_t n, uint32_t up, const KeyParams& kp,
+                             const TableView& tv, int32_t dtype, float* out, uint8_t* level_out,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_query_hier<<<grid_for(n, 256), 256, 0, s>>>(q, n, up, kp, tv, dtype, out, level_out);
   return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ EXPORTS = [
     ("psf_temporal_update", ctypes.c_int, [_vp, _vp]),
     ("psf_query", ctypes.c_int, [_vp, _P(psf_queries), _u64, _vp, _vp, _vp]),
     ("psf_iterate", ctypes.c_int, [_vp, _P(psf_records), _u64, _P(psf_queries), _u64, _vp, _vp, _vp]),
+    ("psf_query_levels", ctypes.c_int, [_vp, _P(psf_queries), _u64, _u32, _vp, _vp, _vp]),
     ("psf_progressive_step", ctypes.c_int, [_vp, _P(psf_records), _P(psf_queries), _P(psf_step_args), _u64,
                                             _vp, _vp]),
     ("psf_reset", ctypes.c_int, [_vp, _u32, _vp]),
@@ -242,6 +243,21 @@ class Table:
         _check(self._lib.psf_query(self.handle, ctypes.byref(qs), n, ctypes.c_void_p(_ptr(out)),
                                    ctypes.c_void_p(_ptr(found)), current_stream()))
         return out, found
+
+    def query_levels(self, q: dict, levels_up: int, n: int | None = None, out=None, level=None):
+        """psf_query_levels: lookup falling back to coarser levels; returns
+        (out (3, n), level (n,): 0 none, else 1 + levels above)."""
+        import torch
+        n = int(q["px"].numel()) if n is None else int(n)
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        if level is None:
+            level = torch.empty(n, dtype=torch.uint8, device="cuda")
+        qs = make_queries(q)
+        _check(self._lib.psf_query_levels(self.handle, ctypes.byref(qs), n, int(levels_up),
+                                          ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_ptr(level)),
+                                          current_stream()))
+        return out, level
 
     def iterate(self, rec: dict, q: dict | None = None, out=None, found=None):
         import torch

@@ -552,3 +552,30 @@ def test_local_counter_reset(psf, torch_cuda, insert_mode):
         t.reset_region((1, 0, 0), (0, 1, 1))
     with pytest.raises(psf.PsfError):
         t.reset_region((0, 0, 0), (float("nan"), 1, 1))
+
+
+def test_multi_level_lookup(psf, torch_cuda):
+    """Cells learned at coarse levels (footprints x 4), queried from finer
+    levels (footprints / 4) with up to 3 levels of climb: the answering level
+    bit for bit, the values within the FP32 tolerance."""
+    from synth import workloads as W
+    wl = W.tiny(alpha_mode=0)
+    sc = W.make_scene(wl)
+    orc = _oracle(wl["table"])
+    t = _table(psf, wl["table"])
+    for it in range(3):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        fp = W.footprints(rec, wl, spread=1.0)
+        coarse = dict(rec, footprint=fp * np.float32(4.0))
+        orc.insert(coarse)
+        orc.update()
+        t.iterate(to_device(coarse))
+    q = dict(rec, footprint=fp * np.float32(0.25))
+    for up in (0, 1, 3):
+        out, level = t.query_levels(to_device(q), up)
+        torch_cuda.cuda.synchronize()
+        w_out, w_level = orc.query_levels(q, up)
+        assert np.array_equal(level.cpu().numpy(), w_level), up
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, up
+    assert int((w_level >= 2).sum()) > 0 and int((w_level == 0).sum()) < len(w_level)

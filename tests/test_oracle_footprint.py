@@ -66,3 +66,40 @@ def test_footprint_of_the_camera_rule_gives_its_level():
     k_fp, _ = by_fp.keys(dict(rec, footprint=width.astype(np.float32)))
     assert keep.mean() > 0.99
     assert np.array_equal(k_cam[keep], k_fp[keep])
+
+
+def test_multi_level_lookup_worked_example():
+    """Sec. 2.3's hierarchy: a cell of edge 1 (level 2 with e_min -2) holds
+    5; a query of footprint 0.25 (level 0, edge 0.25) whose own cell and
+    level-1 cell are empty is answered two levels up."""
+    o = oracle.Oracle(e_min=-2, kappa=0.0)
+    o.insert(records(1, px=0.3, py=0.3, pz=0.3, footprint=1.0, r=5.0, g=5.0, b=5.0))
+    o.update()
+    q = records(1, px=0.6, py=0.1, pz=0.9, footprint=0.25)
+    for up, lv, val in ((0, 0, 0.0), (1, 0, 0.0), (2, 3, 5.0), (5, 3, 5.0)):
+        out, level = o.query_levels(q, up)
+        assert int(level[0]) == lv and np.all(out[:, 0] == val), (up, level, out)
+    # a vertex in the same edge-1 cell but outside it at level 2 is not answered
+    far = records(1, px=1.6, py=0.1, pz=0.9, footprint=0.25)
+    assert int(o.query_levels(far, 4)[1][0]) == 0
+    # the coarsest level stops the climb: a vertex already at max_level has no parents
+    top = oracle.Oracle(e_min=-2, kappa=0.0, max_level=2)
+    top.insert(records(1, px=0.3, py=0.3, pz=0.3, footprint=1.0, r=2.0, g=2.0, b=2.0))
+    top.update()
+    out, level = top.query_levels(records(1, px=0.5, py=0.5, pz=0.5, footprint=8.0), 3)
+    assert int(level[0]) == 1 and np.all(out[:, 0] == 2.0)
+
+
+def test_multi_level_lookup_without_climb_is_the_plain_query():
+    from synth import workloads as W
+    wl = W.tiny()
+    sc = W.make_scene(wl)
+    o = oracle.Oracle(**wl["table"])
+    for it in range(2):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["rough"] = None
+        o.insert(rec)
+        o.update()
+    out0, found = o.query(rec)
+    out1, level = o.query_levels(rec, 0)
+    assert np.array_equal(found, level) and np.array_equal(out0, out1)
