@@ -254,7 +254,10 @@ psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n, const p
  * caller's throughput factor of the sampled step x_i -> x_{i+1}.  The
  * samples are written to d_samples (3*n floats, SoA, caller-owned device
  * memory), inserted at the vertices x and blended, as psf_iterate with no
- * queries would.  x->r, g, b are ignored; le may be NULL (no emission). */
+ * queries would.  x->r, g, b are ignored; le may be NULL (no emission).
+ * Algorithm 2's field L_o\e (radiance minus emission) is the same step with
+ * the emission the sampled step picks up at x_{i+1} (times t_i, plus any
+ * next-event estimate at x_i) passed as le. */
 typedef struct psf_step_args {
   const float *le_r, *le_g, *le_b;  /* emission at x_i (all three or none) */
   const float *t_r, *t_g, *t_b;     /* throughput factor f G w / p */

@@ -66,3 +66,22 @@ def test_step_without_emission_and_invalid_arguments(env):
     x, nx, tp, em = W.furnace_paths(16, 1, 0)
     with pytest.raises(psf.PsfError):
         t.progressive_step(to_device(x), {k: v for k, v in to_device(nx).items() if k != "px"}, _dev_arrays(tp))
+
+
+def test_radiance_minus_emission_field_frames(env):
+    """Algorithm 2's field (emission of the next vertex folded into the
+    step's emission argument) in lockstep with the oracle."""
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    cfg = W.furnace_table()
+    t = psf.Table(**cfg)
+    o = oracle.Oracle(**cfg)
+    for it in range(20):
+        x, nx, tp, em = W.furnace_paths(2048, 2, it)
+        le_next = tuple(a * b for a, b in zip(tp, em))
+        want = oracle.progressive_step(o, x, nx, tp, le_next)
+        got = t.progressive_step(to_device(x), to_device(nx), _dev_arrays(tp), _dev_arrays(le_next))
+        torch.cuda.synchronize()
+        assert rel_err(got.cpu().numpy(), want).max() <= RTOL, it
+    compare_cells(t.export(), o.export(), RTOL)

@@ -47,3 +47,20 @@ def test_without_transport_the_solver_keeps_emission():
         x, nx, tp, em = W.furnace_paths(512, 2, it, le=tuple(LE), albedo=(0.0, 0.0, 0.0))
         oracle.progressive_step(o, x, nx, tp, em)
     assert np.all(o.export()["L"] == LE[:, None])
+
+
+def test_radiance_minus_emission_field_of_algorithm_2():
+    """Algorithm 2 tracks L_o\\e: the sample at x_i picks the emission of the
+    next vertex up through the sampled step instead of its own:
+    Lbar = (L_e(x_{i+1}) + L~o\\e(x_{i+1})) t_i, i.e. the step's emission
+    argument is t_i L_e.  In the furnace its fixed point is
+    L - L_e = rho L_e / (1 - rho)."""
+    o = oracle.Oracle(**W.furnace_table())
+    for it in range(200):
+        x, nx, tp, em = W.furnace_paths(2048, 2, it, le=tuple(LE), albedo=tuple(RHO))
+        le_next = tuple(np.float32(r) * e for r, e in zip(RHO, em))
+        oracle.progressive_step(o, x, nx, tp, le_next)
+    L = o.export()["L"]
+    want = (RHO * LE / (1.0 - RHO))[:, None]
+    rel = np.abs(L / want - 1.0)
+    assert float(np.mean(rel)) < 5e-4 and float(np.percentile(rel, 90)) < 1e-3
