@@ -26,6 +26,8 @@
 //
 // A partition is owned by exactly one block in the merge pass, so the
 // write-back uses plain loads and stores.
+#include <atomic>
+
 #include "psf_device.h"
 #include "psf_internal.h"
 
@@ -715,13 +717,28 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
 static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 24); }
 
 // Raise a kernel's dynamic-LDS limit only as far as the launch needs (and
-// only when it exceeds the default 64 KiB): the limit is per function and is
-// remembered, so it is set once per distinct requirement.
-static hipError_t lds_limit(const void* fn, size_t bytes, int* current) {
-  if (bytes <= 65536 || (int)bytes <= *current) return hipSuccess;
-  hipError_t a = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (a == hipSuccess) *current = (int)bytes;
-  return a;
+// only when it exceeds the default 64 KiB).  The limit belongs to the
+// function on the current device; the largest value set is remembered per
+// device (devices past the table are set on every launch).
+constexpr int kLdsDevices = 64;
+struct LdsLimit {
+  std::atomic<int> bytes[kLdsDevices];
+};
+
+static hipError_t lds_limit(const void* fn, size_t bytes, LdsLimit* cur) {
+  if (bytes <= 65536) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const bool known = dev >= 0 && dev < kLdsDevices;
+  if (known && (int)bytes <= cur->bytes[dev].load(std::memory_order_relaxed)) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess && known) {
+    int prev = cur->bytes[dev].load(std::memory_order_relaxed);
+    while ((int)bytes > prev && !cur->bytes[dev].compare_exchange_weak(prev, (int)bytes)) {
+    }
+  }
+  return e;
 }
 
 static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
@@ -732,7 +749,7 @@ static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
 template <uint32_t kPer, bool kFp>
 static hipError_t launch_bin_t(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
                                const PartView& pv, size_t shm, uint32_t ntiles, hipStream_t s) {
-  static int lim = 0;  // one per instantiation
+  static LdsLimit lim;  // one per instantiation
   hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin<kPer, kFp>), shm, &lim);
   if (e != hipSuccess) return e;
   k_bin<kPer, kFp><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
@@ -765,7 +782,7 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = merge_lds(tv.part_log2);
-  static int lim_f = 0, lim_p = 0;
+  static LdsLimit lim_f, lim_p;
   hipError_t e = fuse ? lds_limit(reinterpret_cast<const void*>(&k_merge<true>), shm, &lim_f)
                       : lds_limit(reinterpret_cast<const void*>(&k_merge<false>), shm, &lim_p);
   if (e != hipSuccess) return e;
@@ -802,7 +819,7 @@ hipError_t launch_unstage(uint64_t n, const TableView& tv, const PartView& pv, f
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = unstage_lds(pv.tile);
-  static int lim = 0;
+  static LdsLimit lim;
   hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_unstage), shm, &lim);
   if (e != hipSuccess) return e;
   k_unstage<<<ntiles, kUnstageThreads, shm, s>>>(pv, P, n, out, found);
@@ -879,7 +896,7 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
 template <uint32_t kPer, bool kFp>
 static hipError_t launch_bin_batch_t(const BatchSession* d_ss, uint32_t k, uint32_t tiles, size_t lds,
                                      hipStream_t s) {
-  static int lim = 0;  // one per instantiation
+  static LdsLimit lim;  // one per instantiation
   hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin_batch<kPer, kFp>), lds, &lim);
   if (e != hipSuccess) return e;
   k_bin_batch<kPer, kFp><<<tiles, kBinThreads, lds, s>>>(d_ss, k);
@@ -914,7 +931,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint
     qblks += S.nqblk;
     trans += S.ntrans;
   }
-  static int lim_m = 0, lim_q = 0;
+  static LdsLimit lim_m, lim_q;
   hipError_t e = fp ? (per == 8    ? launch_bin_batch_t<8, true>(d_ss, k, tiles, lds_b, s)
                        : per == 12 ? launch_bin_batch_t<12, true>(d_ss, k, tiles, lds_b, s)
                                    : launch_bin_batch_t<16, true>(d_ss, k, tiles, lds_b, s))
