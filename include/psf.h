@@ -9,7 +9,7 @@
  *      (Sec. 2.6): every cell accumulates a sample count and a sum of sample
  *      values, the counter c_h^new and the numerator of Eq. 6 with box basis
  *      functions and MIS weight 1 (Algorithm 1: increment_counters,
- *      update_approx);
+ *      update_approx), or, in a weighted table, each record's MIS weight;
  *   2. applies the temporal blend of Sec. 2.4 (Eq. 10-11) to every cell that
  *      received samples: L <- (1 - alpha) L + alpha * mean, with
  *      alpha = max(sqrt(c_new / (c_old + c_new)), 1 / T_max) and the
@@ -145,7 +145,15 @@ typedef struct psf_config {
   uint32_t bin_per;          /* partitioned insert: records per thread of the
                                 binning pass (0 = default 8, else 8, 12, 16);
                                 a binning tile is 512 * bin_per records */
-  uint32_t reserved;         /* must be 0 */
+  uint32_t weighted;         /* 0: every record counts 1 (integer counters).
+                                1: MIS-weighted counters (Eq. 5-6 with
+                                weights w != 1, e.g. a down-weighted field
+                                that keeps only some sampling techniques,
+                                Sec. 2.5): records may carry a weight array;
+                                a cell's counter is the binary32 sum of the
+                                weights that fell on it and its sample mean
+                                the weighted mean; Eq. 11 takes the weighted
+                                counters. */
 } psf_config;
 
 /* Vertex records, structure of arrays, N float32 each (device memory).
@@ -157,7 +165,13 @@ typedef struct psf_config {
  * 2.3 selects the hierarchy level by footprint) and the level is the
  * largest l <= max_level with 2^(e_min + l) <= footprint (0 below 2^e_min)
  * instead of the camera-distance rule; a non-finite or non-positive
- * footprint rejects the record like a non-finite position. */
+ * footprint rejects the record like a non-finite position.  weight may be
+ * NULL (every weight 1); otherwise it is the record's MIS weight (Eq. 5:
+ * the record adds w to its cell's counter and w * (r, g, b) to its sum) and
+ * the table must have been created with weighted = 1 (INVALID_ARGUMENT
+ * otherwise).  A weight that is not finite and > 0 rejects the sample (it
+ * is counted as skipped; as a query vertex of psf_iterate the record is
+ * still answered). */
 typedef struct psf_records {
   const float *px, *py, *pz;
   const float *nx, *ny, *nz;
@@ -165,6 +179,7 @@ typedef struct psf_records {
   const float *r, *g, *b;
   const float *rough;
   const float *footprint;
+  const float *weight;
 } psf_records;
 
 /* Query vertices: the same fields without a sample value. */
@@ -289,7 +304,8 @@ psf_status psf_compute_keys(psf_table* t, const psf_records* rec, uint64_t n, ui
 psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream);
 
 /* Copy every occupied cell to host arrays of capacity cap: keys, pending
- * counts n_new, cumulative counts c_old, approximant (3*cap floats, SoA,
+ * counts n_new, cumulative counts c_old (for a weighted table both hold
+ * binary32 bit patterns: weight sums), approximant (3*cap floats, SoA,
  * decoded to float).  Any output pointer except keys may be NULL.  *count
  * receives the number of occupied cells; BUFFER_TOO_SMALL if it exceeds cap
  * (nothing is written then).  Order is unspecified.  Synchronises stream. */

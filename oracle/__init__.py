@@ -5,9 +5,9 @@ CPU-baseline leg may use it; the library never does.  The arithmetic lives in
 ``psf_oracle.cpp`` (binary64, ``std::map``); this module only marshals numpy
 arrays through ctypes.  It imports nothing from the HIP package.
 
-Sections followed: Sec. 2.1 Eq. 5-6 (counts and weighted means per basis
-function), Sec. 2.4 Eq. 10-11 (temporal blend, counter reset), Sec. 2.6
-(spatio-directional hashing; the key specification is this project's, written
+Sections followed: Sec. 2.1 Eq. 5-6 (counters and weighted means per basis
+function, with optional per-record MIS weights: Sec. 2.5), Sec. 2.4 Eq. 10-11
+(temporal blend, counter reset), Sec. 2.6 (spatio-directional hashing; the key specification is this project's, written
 out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state),
 and, for the two-field estimators, Sec. 2.5, Sec. 4.2 (Eq. 25) and Sec. 5
 (Eq. 28) in ``estimate`` below (plain numpy in binary64 over the lookups).
@@ -25,11 +25,12 @@ _lib = None
 
 ALPHA_PAPER, ALPHA_CONST, ALPHA_LINEAR = 0, 1, 2
 RESET_COUNTERS, RESET_CLEAR = 1, 2
-FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
+FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint",
+          "weight")
 
 
 class _Records(ctypes.Structure):
-    _fields_ = [("f", ctypes.c_void_p * 14)]
+    _fields_ = [("f", ctypes.c_void_p * 15)]
 
 
 def build(force: bool = False) -> str:
@@ -96,7 +97,11 @@ class Oracle:
 
     def __init__(self, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0, max_level=15,
                  normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
-                 alpha_mode=ALPHA_PAPER, alpha=0.2, t_max=5.0, **_ignored):
+                 alpha_mode=ALPHA_PAPER, alpha=0.2, t_max=5.0, weighted=0, **_ignored):
+        # weighted: records may carry MIS weights and the exported counters
+        # are float64 weight sums; otherwise they are integer counts (uint64)
+        # and a weight array is refused, as the library refuses it
+        self.weighted = bool(weighted)
         self._lib = _load()
         cam_arr = (ctypes.c_float * 3)(*[float(c) for c in cam])
         self._h = self._lib.orc_create(cam_arr, float(np.float32(kappa)), int(e_min),
@@ -133,6 +138,8 @@ class Oracle:
         self._lib.orc_set_filter(self._h, k.ctypes.data if k.size else None, int(k.size))
 
     def insert(self, rec):
+        if rec.get("weight") is not None and not self.weighted:
+            raise ValueError("weights need a weighted table")
         n = self._n(rec)
         p = _Pack(rec, n)
         self._lib.orc_insert(self._h, ctypes.byref(p.s), n)
@@ -174,14 +181,17 @@ class Oracle:
     def export(self):
         cap = self.count()
         keys = np.zeros(cap, dtype=np.uint64)
-        n_new = np.zeros(cap, dtype=np.uint64)
-        c_old = np.zeros(cap, dtype=np.uint64)
+        n_new = np.zeros(cap, dtype=np.float64)
+        c_old = np.zeros(cap, dtype=np.float64)
         L = np.zeros((3, cap), dtype=np.float64)
         s = np.zeros((3, cap), dtype=np.float64)
         if cap:
             got = self._lib.orc_export(self._h, keys.ctypes.data, n_new.ctypes.data,
                                        c_old.ctypes.data, L.ctypes.data, s.ctypes.data, cap)
             assert got == cap
+        if not self.weighted:
+            # unit weights: the counters are integers, exact in binary64
+            n_new, c_old = n_new.astype(np.uint64), c_old.astype(np.uint64)
         return {"keys": keys, "n_new": n_new, "c_old": c_old, "L": L, "s": s}
 
     def counters(self):

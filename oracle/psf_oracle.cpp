@@ -10,8 +10,11 @@
 // spatio-temporal filtering", arXiv 2005.07547):
 //   * Sec. 2.1, Eq. 5-6: per basis function h, a counter c_h (sum of box-basis
 //     memberships times MIS weights) and the weighted sample mean of the path
-//     tail estimates.  Box basis, weight w = 1 (Algorithm 1 sets the MIS
-//     weight to 1 when no other technique is used).
+//     tail estimates.  Box basis; weight w = 1 unless the records carry MIS
+//     weights (Algorithm 1 sets the weight to 1 when no other technique is
+//     used; Sec. 2.5 allows fields fed by only some techniques, whose weights
+//     then do not sum to one).  A weight must be finite and > 0, else the
+//     sample is skipped.
 //   * Sec. 2.4, Eq. 10-11: temporal blend of the new mean into the previous
 //     approximant with alpha = max(sqrt(c_new / (c_old + c_new)), 1/T_max);
 //     c_old is the cumulative count up to the previous frame.  The same
@@ -58,9 +61,9 @@ struct Config {
 };
 
 struct Cell {
-  uint64_t n_new = 0;            // c_h^new of the current frame
-  double s[3] = {0.0, 0.0, 0.0}; // sum of the frame's sample values
-  uint64_t c_old = 0;            // cumulative count up to the previous frame
+  double n_new = 0.0;            // c_h^new of the current frame (sum of weights)
+  double s[3] = {0.0, 0.0, 0.0}; // sum of the frame's weighted sample values
+  double c_old = 0.0;            // cumulative counter up to the previous frame
   double L[3] = {0.0, 0.0, 0.0}; // approximant
 };
 
@@ -211,11 +214,10 @@ KeyResult key_of(const Config& c, float px, float py, float pz, float nx, float 
   return r;
 }
 
-double alpha_of(const Config& c, uint64_t n_new, uint64_t c_old) {
-  double n = (double)n_new, o = (double)c_old;
+double alpha_of(const Config& c, double n, double o) {
   switch (c.alpha_mode) {
     case 1:  // constant alpha (exponential weighting); first touch takes the mean
-      return c_old == 0 ? 1.0 : (double)c.alpha;
+      return o == 0.0 ? 1.0 : (double)c.alpha;
     case 2:  // linear accumulation
       return n / (o + n);
     default: {  // Eq. 11
@@ -230,11 +232,12 @@ double alpha_of(const Config& c, uint64_t n_new, uint64_t c_old) {
 
 extern "C" {
 
-// Record arrays: 14 pointers px,py,pz,nx,ny,nz,ox,oy,oz,r,g,b,rough,footprint.
-// Any of ox..oz, r..b, rough and footprint may be null where not used (rough
-// null = diffuse, footprint null = level from the camera distance).
+// Record arrays: 15 pointers px,py,pz,nx,ny,nz,ox,oy,oz,r,g,b,rough,footprint,
+// weight.  Any of ox..oz, r..b, rough, footprint and weight may be null where
+// not used (rough null = diffuse, footprint null = level from the camera
+// distance, weight null = every MIS weight 1).
 struct orc_records {
-  const float* f[14];
+  const float* f[15];
 };
 
 void* orc_create(const float* cam, float kappa, int e_min, int max_level, int normal_bins_log2,
@@ -284,24 +287,28 @@ void orc_set_filter(void* h, const uint64_t* keys, uint64_t n) {
   for (uint64_t i = 0; i < n; ++i) o->filter.insert(keys[i]);
 }
 
-// Eq. 5-6 with box basis and w = 1: count and sum per cell, in array order.
+// Eq. 5-6 with box basis: per cell, the counter (sum of the MIS weights w of
+// its samples, 1 each without weights) and the sum of w times the sample
+// value, in array order.
 void orc_insert(void* h, const orc_records* r, uint64_t n) {
   Oracle* o = static_cast<Oracle*>(h);
   const float* const* f = r->f;
   for (uint64_t i = 0; i < n; ++i) {
     float R = f[9][i], G = f[10][i], B = f[11][i];
+    float w = f[14] ? f[14][i] : 1.0f;
     KeyResult k = key_at(o->cfg, r, i);
-    if (!k.valid || !finite3(R, G, B)) {
+    if (!k.valid || !finite3(R, G, B) || !(std::isfinite(w) && w > 0.0f)) {
       o->skipped++;
       continue;
     }
     if (k.overflow) o->coord_overflow++;
     if (o->filtered && o->filter.count(k.key) == 0) continue;
     Cell& c = o->cells[k.key];
-    c.n_new += 1;
-    c.s[0] += (double)R;
-    c.s[1] += (double)G;
-    c.s[2] += (double)B;
+    const double wd = (double)w;
+    c.n_new += wd;
+    c.s[0] += wd * (double)R;
+    c.s[1] += wd * (double)G;
+    c.s[2] += wd * (double)B;
     o->inserted++;
   }
 }
@@ -313,15 +320,15 @@ uint64_t orc_update(void* h) {
   uint64_t touched = 0;
   for (auto& kv : o->cells) {
     Cell& c = kv.second;
-    if (c.n_new == 0) continue;
+    if (c.n_new == 0.0) continue;
     double a = alpha_of(o->cfg, c.n_new, c.c_old);
     for (int ch = 0; ch < 3; ++ch) {
-      double mean = c.s[ch] / (double)c.n_new;
+      double mean = c.s[ch] / c.n_new;
       c.L[ch] = (1.0 - a) * c.L[ch] + a * mean;
       c.s[ch] = 0.0;
     }
     c.c_old += c.n_new;
-    c.n_new = 0;
+    c.n_new = 0.0;
     touched++;
   }
   return touched;
@@ -337,7 +344,7 @@ void orc_query(void* h, const orc_records* r, uint64_t n, double* out_rgb, uint8
     uint8_t hit = 0;
     if (k.valid) {
       auto it = o->cells.find(k.key);
-      if (it != o->cells.end() && it->second.c_old > 0) {
+      if (it != o->cells.end() && it->second.c_old > 0.0) {
         hit = 1;
         for (int ch = 0; ch < 3; ++ch) v[ch] = it->second.L[ch];
       }
@@ -363,7 +370,7 @@ void orc_query_levels(void* h, const orc_records* r, uint64_t n, int up, double*
       KeyResult kr = key_at(o->cfg, r, i, k);
       if (!kr.valid) break;
       auto it = o->cells.find(kr.key);
-      if (it != o->cells.end() && it->second.c_old > 0) {
+      if (it != o->cells.end() && it->second.c_old > 0.0) {
         for (int ch = 0; ch < 3; ++ch) v[ch] = it->second.L[ch];
         lv = (uint8_t)(k + 1);
         break;
@@ -383,7 +390,7 @@ void orc_reset(void* h, uint32_t what) {
     return;
   }
   if (what & 1u)
-    for (auto& kv : o->cells) kv.second.c_old = 0;
+    for (auto& kv : o->cells) kv.second.c_old = 0.0;
 }
 
 // Local counter reset (Sec. 2.4: counters zeroed locally, on demand): every
@@ -405,15 +412,16 @@ void orc_reset_region(void* h, const float* lo, const float* hi) {
     float s = std::ldexp(1.0f, o->cfg.e_min + lvl);
     if (cell_meets_axis(key, 0, s, lo[0], hi[0]) && cell_meets_axis(key, 16, s, lo[1], hi[1]) &&
         cell_meets_axis(key, 32, s, lo[2], hi[2]))
-      kv.second.c_old = 0;
+      kv.second.c_old = 0.0;
   }
 }
 
 uint64_t orc_count(void* h) { return static_cast<Oracle*>(h)->cells.size(); }
 
-// Cells in ascending key order.  L and s are 3 x cap (SoA).  Returns the
-// number written.
-uint64_t orc_export(void* h, uint64_t* keys, uint64_t* n_new, uint64_t* c_old, double* L,
+// Cells in ascending key order.  L and s are 3 x cap (SoA); the counters
+// are sums of weights (integers without weights).  Returns the number
+// written.
+uint64_t orc_export(void* h, uint64_t* keys, double* n_new, double* c_old, double* L,
                     double* s, uint64_t cap) {
   Oracle* o = static_cast<Oracle*>(h);
   uint64_t i = 0;

@@ -26,7 +26,8 @@ PSF_FLAG_TRANSPOSE_RUNS = 4
 PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 
-REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint")
+REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint",
+              "weight")
 QRY_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough", "footprint")
 EST_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "oox", "ooy", "ooz", "oix", "oiy", "oiz", "rough",
               "gr", "gg", "gb", "wp", "footprint")
@@ -47,7 +48,7 @@ class psf_config(ctypes.Structure):
         ("alpha_mode", ctypes.c_int32), ("alpha", ctypes.c_float), ("t_max", ctypes.c_float),
         ("state_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("insert_mode", ctypes.c_int32), ("part_log2", ctypes.c_uint32),
-        ("max_batch", ctypes.c_uint64), ("bin_per", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint64), ("bin_per", ctypes.c_uint32), ("weighted", ctypes.c_uint32),
     ]
 
 
@@ -144,7 +145,7 @@ def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_m
                 max_level=15, normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
                 alpha_mode=PSF_ALPHA_PAPER, alpha=0.2, t_max=5.0, state_dtype=PSF_STATE_F32,
                 flags=0, insert_mode=PSF_INSERT_AUTO, part_log2=0, max_batch=0, bin_per=0,
-                **_ignored):
+                weighted=0, **_ignored):
     c = psf_config()
     c.log2_slots, c.max_probe = int(log2_slots), int(max_probe)
     c.cam[:] = [float(x) for x in cam]
@@ -153,6 +154,7 @@ def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_m
     c.rough_thr, c.alpha_mode, c.alpha, c.t_max = float(rough_thr), int(alpha_mode), float(alpha), float(t_max)
     c.state_dtype, c.flags, c.insert_mode = int(state_dtype), int(flags), int(insert_mode)
     c.part_log2, c.max_batch, c.bin_per = int(part_log2), int(max_batch), int(bin_per)
+    c.weighted = int(weighted)
     return c
 
 
@@ -332,7 +334,8 @@ class Table:
                 for k in range(PSF_K_COUNT) if launches[k]}
 
     def export(self):
-        """Occupied cells as numpy arrays: keys (uint64), n_new, c_old, L (3 x C)."""
+        """Occupied cells as numpy arrays: keys (uint64), n_new, c_old (uint32
+        counts; float32 weight sums for a weighted table), L (3 x C)."""
         import numpy as np
         st = self.stats()
         cap = max(1, int(st["occupied"]))
@@ -346,6 +349,8 @@ class Table:
                                           ctypes.byref(count), current_stream()))
         c = int(count.value)
         order = np.argsort(keys[:c], kind="stable")
+        if self.cfg.weighted:
+            n_new, c_old = n_new.view(np.float32), c_old.view(np.float32)
         return {"keys": keys[:c][order], "n_new": n_new[:c][order], "c_old": c_old[:c][order],
                 "L": rgb[:, :c][:, order]}
 

@@ -243,3 +243,18 @@ def furnace_paths(n_paths: int, verts: int, it: int, seed: int = 9, le=(1.0, 0.5
 def furnace_table(log2_slots: int = 16) -> dict:
     """Fixed-level table for the furnace (edge 1/8, 4 x 4 normal bins)."""
     return _table(log2_slots, (0.0, 0.0, 0.0), 60.0, 64, 1.0, -3) | {"kappa": 0.0}
+
+
+def mis_weights(n: int, seed: int = 21, excluded: float = 0.1) -> np.ndarray:
+    """Per-record MIS weights standing in for a field fed by some of a
+    renderer's sampling techniques: the balance-heuristic weight of one of two
+    techniques whose densities at the sample are independent lognormal(0, 1)
+    draws, p1 / (p1 + p2), in (0, 1); a fraction `excluded` of the records
+    come from a technique the field leaves out (weight 0, rejected by the
+    insert).  Seeded, binary32."""
+    rng = np.random.default_rng(seed)
+    p1 = rng.lognormal(0.0, 1.0, n)
+    p2 = rng.lognormal(0.0, 1.0, n)
+    w = (p1 / (p1 + p2)).astype(np.float32)
+    w[rng.random(n) < excluded] = 0.0
+    return w
