@@ -146,13 +146,13 @@ bool validate(const psf_config* c, std::string* why) {
     return bad("unknown flags");
   if (c->max_batch > (1ull << 31)) return bad("max_batch must be <= 2^31");
   if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
-  if (c->reserved != 0) return bad("reserved must be 0");
+  if (c->weighted > 1) return bad("weighted must be 0 or 1");
   return true;
 }
 
 struct Layout {
-  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, runs = 0, runs_t = 0,
-         perm = 0, total = 0;
+  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, stage_w = 0, runs = 0,
+         runs_t = 0, perm = 0, total = 0;
   uint32_t part_log2 = 0;
   bool part = false;
   uint64_t cap = 0;
@@ -186,6 +186,10 @@ Layout layout_of(const psf_config& c) {
     off = align_up(off + L.cap * 8, 256);
     L.stage_rgb = off;
     off = align_up(off + L.cap * 12, 256);
+    if (c.weighted) {
+      L.stage_w = off;
+      off = align_up(off + L.cap * 4, 256);
+    }
     L.runs = off;
     off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
     L.runs_t = off;  // rows padded to a multiple of 4 tiles (16-byte loads)
@@ -197,8 +201,9 @@ Layout layout_of(const psf_config& c) {
   return L;
 }
 
-bool rec_ok(const psf_records* r, std::string* why) {
+bool rec_ok(const psf_records* r, const psf_table* t, std::string* why) {
   if (!r) return (*why = "records is NULL", false);
+  if (r->weight && !t->cfg.weighted) return (*why = "record weights need a table created with weighted = 1", false);
   if (!r->px || !r->py || !r->pz || !r->nx || !r->ny || !r->nz)
     return (*why = "position and normal arrays are required", false);
   if (!r->r || !r->g || !r->b) return (*why = "r, g, b arrays are required", false);
@@ -218,7 +223,7 @@ bool qry_ok(const psf_queries* q, std::string* why) {
 
 psf::RecPtrs rec_ptrs(const psf_records* r) {
   return psf::RecPtrs{r->px, r->py, r->pz, r->nx, r->ny, r->nz, r->ox, r->oy, r->oz,
-                      r->r,  r->g,  r->b,  r->rough, r->footprint};
+                      r->r,  r->g,  r->b,  r->rough, r->footprint, r->weight};
 }
 
 psf::QryPtrs qry_ptrs(const psf_queries* q) {
@@ -233,8 +238,8 @@ uint64_t nslots(const psf_table* t) { return 1ull << t->cfg.log2_slots; }
 
 psf::RecPtrs offset_rec(const psf::RecPtrs& rp, uint64_t off) {
   psf::RecPtrs sub = rp;
-  const float** f[] = {&sub.px, &sub.py, &sub.pz, &sub.nx, &sub.ny, &sub.nz, &sub.ox,
-                       &sub.oy, &sub.oz, &sub.r,  &sub.g,  &sub.b,  &sub.rough};
+  const float** f[] = {&sub.px, &sub.py, &sub.pz, &sub.nx,    &sub.ny,       &sub.nz,    &sub.ox, &sub.oy,
+                       &sub.oz, &sub.r,  &sub.g,  &sub.b,     &sub.rough,    &sub.footprint, &sub.weight};
   for (auto* p : f)
     if (*p) *p += off;
   return sub;
@@ -254,6 +259,7 @@ psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream
       const psf::RecPtrs sub = offset_rec(rp, off);
       psf::PartView pv = t->pv;
       pv.perm = nullptr;
+      if (!sub.weight) pv.stage_w = nullptr;
       const uint32_t nt = (uint32_t)((m + pv.tile - 1) / pv.tile);
       if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
       e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(sub, m, t->kp, t->tv, pv, s); });
@@ -344,7 +350,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   t->tv.log2_slots = cfg->log2_slots;
   t->tv.part_log2 = L.part_log2;
   t->tv.max_probe = cfg->max_probe < (1u << L.part_log2) ? cfg->max_probe : (1u << L.part_log2);
-  t->tv.flags = cfg->flags;
+  t->tv.flags = cfg->flags | (cfg->weighted ? psf::kTvWeighted : 0u);
   t->kp = psf::KeyParams{cfg->cam[0], cfg->cam[1], cfg->cam[2], cfg->kappa, cfg->e_min,
                          cfg->max_level, cfg->normal_bins_log2, cfg->dir_bins_log2, cfg->rough_thr};
   t->bp = psf::BlendParams{cfg->alpha_mode, cfg->alpha, 1.0f / cfg->t_max, cfg->state_dtype};
@@ -352,6 +358,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if (L.part) {
     t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
     t->pv.stage_rgb = reinterpret_cast<float*>(b + L.stage_rgb);
+    t->pv.stage_w = cfg->weighted ? reinterpret_cast<float*>(b + L.stage_w) : nullptr;
     t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
     t->pv.runs_t = reinterpret_cast<uint32_t*>(b + L.runs_t);
     t->pv.perm = reinterpret_cast<uint16_t*>(b + L.perm);
@@ -402,7 +409,7 @@ PSF_API psf_status psf_insert_samples(psf_table* t, const psf_records* rec, uint
   std::string why;
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
   if (n == 0) return PSF_OK;
-  if (!rec_ok(rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (!rec_ok(rec, t, &why)) return fail(PSF_INVALID_ARGUMENT, why);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   return do_insert(t, rec_ptrs(rec), n, s);
@@ -431,7 +438,7 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
                                uint64_t nq, float* d_out_rgb, uint8_t* d_out_found, psf_stream stream) {
   std::string why;
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
-  if (n > 0 && !rec_ok(rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (n > 0 && !rec_ok(rec, t, &why)) return fail(PSF_INVALID_ARGUMENT, why);
   if (nq > 0 && !qry_ok(q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
   if (nq > 0 && !d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -445,6 +452,7 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
     const bool fq = nq == n && same_vertices(rec, q);
     psf::PartView pv = t->pv;
     if (!fq) pv.perm = nullptr;
+    if (!rp.weight) pv.stage_w = nullptr;
     const uint32_t nt = (uint32_t)((n + pv.tile - 1) / pv.tile);
     if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
     hipError_t e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(rp, n, t->kp, t->tv, pv, s); });
@@ -517,6 +525,8 @@ PSF_API psf_status psf_progressive_step(psf_table* t, const psf_records* x, cons
     return fail(PSF_INVALID_ARGUMENT, "vertex position and normal arrays are required");
   if (x->rough && (!x->ox || !x->oy || !x->oz))
     return fail(PSF_INVALID_ARGUMENT, "direction arrays are required when roughness is given");
+  if (x->weight && !t->cfg.weighted)
+    return fail(PSF_INVALID_ARGUMENT, "record weights need a table created with weighted = 1");
   if (!qry_ok(next, &why)) return fail(PSF_INVALID_ARGUMENT, why);
   if (!a || !a->t_r || !a->t_g || !a->t_b) return fail(PSF_INVALID_ARGUMENT, "throughput arrays are required");
   if ((a->le_r != nullptr) != (a->le_g != nullptr) || (a->le_r != nullptr) != (a->le_b != nullptr))
@@ -698,7 +708,7 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
   for (uint32_t i = 0; i < k; ++i) {
     const psf_session& ss = sessions[i];
     if (!ss.table) return fail(PSF_INVALID_ARGUMENT, "session table is NULL");
-    if (ss.n > 0 && !rec_ok(&ss.rec, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+    if (ss.n > 0 && !rec_ok(&ss.rec, ss.table, &why)) return fail(PSF_INVALID_ARGUMENT, why);
     if (ss.nq > 0 && !qry_ok(&ss.q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
     if (ss.nq > 0 && !ss.d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "session output is NULL");
     for (uint32_t j = 0; j < i; ++j)
@@ -748,6 +758,7 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
     d.found = ss.d_out_found;
     d.fused_query = (ss.nq == ss.n && same_vertices(&ss.rec, &ss.q)) ? 1 : 0;
     if (!d.fused_query) d.pv.perm = nullptr;
+    if (!d.rec.weight) d.pv.stage_w = nullptr;
     d.tile_begin = tiles;
     d.ntiles = (uint32_t)((ss.n + t->pv.tile - 1) / t->pv.tile);
     d.part_begin = parts;

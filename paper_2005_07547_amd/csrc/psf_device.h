@@ -28,12 +28,15 @@ struct KeyParams {
 // One table slot, 32 bytes: everything a lookup needs sits in one sector.
 struct alignas(32) Slot {
   unsigned long long key;  // kEmpty when free
-  uint32_t c_old;          // cumulative sample count (Sec. 2.4, c_h^old)
+  uint32_t c_old;          // cumulative counter (Sec. 2.4, c_h^old): a sample
+                           // count, or in a weighted table the binary32 bits
+                           // of a weight sum (0 bits = 0 either way)
   uint32_t pad;
   uint32_t L[4];           // approximant: 3 x f32, or 3 x 16-bit packed in L[0..1]
 };
 
-// Per-slot accumulator of the current frame (Eq. 5-6 numerator / counter).
+// Per-slot accumulator of the current frame (Eq. 5-6 numerator / counter;
+// n holds binary32 bits of the weight sum in a weighted table).
 struct alignas(16) Acc {
   uint32_t n;
   float s[3];
@@ -68,8 +71,23 @@ struct TableView {
   uint32_t log2_slots;
   uint32_t part_log2;        // slots per partition = 2^part_log2 (<= log2_slots)
   uint32_t max_probe;
-  uint32_t flags;
+  uint32_t flags;            // public PSF_FLAG_* bits | kTvWeighted
 };
+
+// TableView::flags bit of a table with MIS-weighted (binary32) counters.
+constexpr uint32_t kTvWeighted = 1u << 16;
+
+__host__ __device__ __forceinline__ bool weighted(const TableView& tv) { return (tv.flags & kTvWeighted) != 0; }
+
+// A counter word as a number: a count, or a weight sum's binary32 bits.
+__device__ __forceinline__ float counter_value(uint32_t c, bool wtd) {
+  return wtd ? __uint_as_float(c) : (float)c;
+}
+
+// c_old + n as a counter word (the weight sum rounds once, to binary32).
+__device__ __forceinline__ uint32_t counter_add(uint32_t c, uint32_t n, bool wtd) {
+  return wtd ? __float_as_uint(__uint_as_float(c) + __uint_as_float(n)) : c + n;
+}
 
 struct BlendParams {
   int32_t mode;     // 0 Eq. 11, 1 constant alpha, 2 linear
@@ -334,11 +352,12 @@ __device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, u
   return key;
 }
 
-// Eq. 10-11 for one cell, FP32.  n > 0.
-__device__ __forceinline__ float blend_alpha(const BlendParams& bp, uint32_t n, uint32_t c_old) {
-  const float nf = (float)n;
+// Eq. 10-11 for one cell, FP32, on counter words (counts, or weight sums
+// in a weighted table).  n > 0.
+__device__ __forceinline__ float blend_alpha(const BlendParams& bp, uint32_t n, uint32_t c_old, bool wtd) {
   if (bp.mode == 1) return c_old == 0 ? 1.0f : bp.alpha;
-  const float ratio = nf / ((float)c_old + nf);
+  const float nf = counter_value(n, wtd);
+  const float ratio = nf / (counter_value(c_old, wtd) + nf);
   if (bp.mode == 2) return ratio;
   return fmaxf(sqrtf(ratio), bp.inv_t_max);
 }

@@ -74,13 +74,16 @@ __global__ void __launch_bounds__(256) k_keys(RecPtrs rec, uint64_t n, KeyParams
 // ------------------------------------------------------------------ direct insert
 // One record per lane.  Lanes of a wave holding the same key elect the lowest
 // lane as leader; sums are merged in LDS; each leader claims its slot with a
-// 64-bit CAS and adds the merged count and sums with global atomics.
+// 64-bit CAS and adds the merged count and sums with global atomics.  In a
+// weighted table the sums are of w * value and the counter adds the weights
+// (binary32 atomics on the counter word).
 constexpr int kInsBlock = 256;
 
 __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64_t n, KeyParams kp,
                                                              TableView tv) {
   __shared__ float s_sum[kInsBlock][3];
   __shared__ uint32_t s_cnt[kInsBlock];
+  __shared__ float s_w[kInsBlock];
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
@@ -89,6 +92,8 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   if (stats && tid < 16) s_hist[tid] = 0;
   s_sum[tid][0] = s_sum[tid][1] = s_sum[tid][2] = 0.0f;
   s_cnt[tid] = 0;
+  s_w[tid] = 0.0f;
+  const bool wtd = weighted(tv);
   __syncthreads();
 
   const uint64_t i = (uint64_t)blockIdx.x * kInsBlock + tid;
@@ -96,7 +101,7 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   bool skip = false;
   uint64_t key = kEmpty;
   bool ovf = false;
-  float r = 0.0f, g = 0.0f, b = 0.0f;
+  float r = 0.0f, g = 0.0f, b = 0.0f, w = 1.0f;
   if (i < n) {
     const bool hr = rec.rough != nullptr;
     const float ro = hr ? rec.rough[i] : 0.0f;
@@ -109,6 +114,13 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
                      gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro, hf,
                      hf ? rec.footprint[i] : 0.0f, key, ovf);
     valid = valid && finite3(r, g, b);
+    if (rec.weight) {
+      w = rec.weight[i];
+      valid = valid && __builtin_isfinite(w) && w > 0.0f;
+      r *= w;
+      g *= w;
+      b *= w;
+    }
     skip = !valid;
   }
   wave_count(&tv.stats->skipped, skip);
@@ -127,6 +139,7 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   }
   if (valid) {
     atomicAdd(&s_cnt[wbase + leader], 1u);
+    if (wtd) atomicAdd(&s_w[wbase + leader], w);
     atomicAdd(&s_sum[wbase + leader][0], r);
     atomicAdd(&s_sum[wbase + leader][1], g);
     atomicAdd(&s_sum[wbase + leader][2], b);
@@ -142,7 +155,10 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
     slot = find_or_claim(tv, key, &probes);
     if (slot != ~0ull) {
       Acc* a = &tv.acc[slot];
-      atomicAdd(&a->n, cnt);
+      if (wtd)
+        atomicAdd(reinterpret_cast<float*>(&a->n), s_w[tid]);
+      else
+        atomicAdd(&a->n, cnt);
       atomicAdd(&a->s[0], s_sum[tid][0]);
       atomicAdd(&a->s[1], s_sum[tid][1]);
       atomicAdd(&a->s[2], s_sum[tid][2]);
@@ -164,10 +180,11 @@ __device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParam
                                            bool& sat) {
   const Acc a = tv.acc[s];
   if (a.n == 0) return false;
+  const bool wtd = weighted(tv);
   Slot* d = &tv.slots[s];
   const uint32_t c_old = d->c_old;
-  const float alpha = blend_alpha(bp, a.n, c_old);
-  const float inv = 1.0f / (float)a.n;
+  const float alpha = blend_alpha(bp, a.n, c_old, wtd);
+  const float inv = 1.0f / counter_value(a.n, wtd);
   float L[3];
   load_state(*d, bp.dtype, L[0], L[1], L[2]);
   float out[3];
@@ -177,7 +194,7 @@ __device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParam
   }
   uint32_t enc[4];
   encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
-  d->c_old = c_old + a.n;
+  d->c_old = counter_add(c_old, a.n, wtd);
   *reinterpret_cast<uint4*>(d->L) = make_uint4(enc[0], enc[1], enc[2], enc[3]);
   tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
   return true;

@@ -86,11 +86,16 @@ __device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_
 // every record knows its place, the tile's staging buffer (tile * 12 bytes:
 // keys, then rgb triples), so that both global writes of the partition-
 // sorted tile are coalesced.
-// kFp: the records carry footprints (their level rule); a separate
-// instantiation keeps the load and its registers out of the common case.
-template <uint32_t kPer, bool kFp>
+// kX: what the records carry beyond the common fields, kXFootprint (their
+// level rule) and kXWeight (MIS weights: the staged values are w * rgb and
+// the weights are staged as well); separate instantiations keep the extra
+// loads and their registers out of the common case.
+constexpr uint32_t kXFootprint = 1, kXWeight = 2;
+
+template <uint32_t kPer, uint32_t kX>
 __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
                                          const TableView& tv, const PartView& pv, uint32_t tile) {
+  constexpr bool kFp = (kX & kXFootprint) != 0, kW = (kX & kXWeight) != 0;
   extern __shared__ uint32_t s_dyn_bin[];
   __shared__ uint32_t s_wave[kBinThreads / 64 + 1];
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
@@ -105,6 +110,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   uint64_t key[kPer];
   uint32_t pos[kPer];  // partition << 16 | rank, then the slot in the sorted tile; ~0 if unused
   float rgb[kPer][3];
+  float wt[kPer];
   uint32_t n_skip = 0, n_ovf = 0;
   const bool hr = rec.rough != nullptr;
   // Every load is unconditional (indices past the end are clamped, absent
@@ -118,7 +124,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
 #pragma unroll
   for (uint32_t j0 = 0; j0 < kPer; j0 += kLoad) {
     float f[kLoad][13];
-    float fp[kLoad];
+    float fp[kLoad], fw[kLoad];
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint64_t i = t0 + (uint64_t)(j0 + q) * kBinThreads + tid;
@@ -137,6 +143,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       f[q][11] = rec.b[ic];
       f[q][12] = p_ro[ic];
       fp[q] = kFp ? rec.footprint[ic] : 0.0f;
+      fw[q] = kW ? rec.weight[ic] : 1.0f;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
@@ -148,7 +155,8 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       uint64_t k;
       const bool kv = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
                                f[q][7], f[q][8], hr, f[q][12], kFp, fp[q], k, ovf);
-      const bool sv = finite3(f[q][9], f[q][10], f[q][11]);
+      const bool sv = finite3(f[q][9], f[q][10], f[q][11]) &&
+                      (!kW || (__builtin_isfinite(fw[q]) && fw[q] > 0.0f));
       if (!(kv && sv)) ++n_skip;
       // a record whose sample is rejected but whose key is valid is still a
       // query vertex: with the fused query it is staged for lookup only
@@ -158,9 +166,10 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       const uint32_t rank = atomicAdd(&s_hist[p], 1u);
       key[j] = sv ? k : k | kLookupOnlyBit;
       pos[j] = (p << 16) | rank;
-      rgb[j][0] = f[q][9];
-      rgb[j][1] = f[q][10];
-      rgb[j][2] = f[q][11];
+      rgb[j][0] = kW ? f[q][9] * fw[q] : f[q][9];
+      rgb[j][1] = kW ? f[q][10] * fw[q] : f[q][10];
+      rgb[j][2] = kW ? f[q][11] * fw[q] : f[q][11];
+      wt[j] = fw[q];
     }
   }
   // rare-event counters: one atomic per wave when non-zero
@@ -205,12 +214,20 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   __syncthreads();
   float* dst = pv.stage_rgb + 3 * t0;
   for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
+  if (kW) {
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j)
+      if (pos[j] != ~0u) s_f[pos[j]] = wt[j];
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_w[t0 + i] = s_f[i];
+  }
 }
 
-template <uint32_t kPer, bool kFp>
+template <uint32_t kPer, uint32_t kX>
 __global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
                                                      TableView tv, PartView pv) {
-  bin_body<kPer, kFp>(rec, n, kp, tv, pv, blockIdx.x);
+  bin_body<kPer, kX>(rec, n, kp, tv, pv, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ run table transpose
@@ -279,7 +296,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
                                            const BlendParams& bp, uint32_t blk, bool results) {
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
   // than f32 ones on gfx950 and exact enough to make the sum order
-  // immaterial).  After the blend the sums hold the cells' new values.
+  // immaterial).  After the blend the sums hold the cells' new values.  In
+  // a weighted table cnt holds binary32 weight sums.
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
@@ -290,6 +308,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   const uint32_t p = xcd_partition(blk, P);
   const uint64_t base = (uint64_t)p << tv.part_log2;
   const bool stats = (tv.flags & 1u) != 0;
+  const bool wtd = weighted(tv);
   unsigned long long* s_key = s_dyn;
   uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_key + B);
   double* s_sum0 = reinterpret_cast<double*>(s_cnt + B);  // B >= 256: 8-byte aligned
@@ -429,13 +448,14 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 
   const uint32_t batches = for_each_batch([&](const uint64_t* at, const bool* ev, uint32_t nb) {
     unsigned long long ek[kEntryBatch];
-    float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch];
+    float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch], ew[kEntryBatch];
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       ek[q] = pv.stage_key[at[q]];
       er[q] = pv.stage_rgb[3 * at[q]];
       eg[q] = pv.stage_rgb[3 * at[q] + 1];
       eb[q] = pv.stage_rgb[3 * at[q] + 2];
+      ew[q] = pv.stage_w ? pv.stage_w[at[q]] : 1.0f;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
@@ -459,7 +479,10 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           atomicAdd(&s_dropped, 1u);
         } else {
           if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
-          atomicAdd(&s_cnt[slot], 1u);
+          if (wtd)
+            atomicAdd(reinterpret_cast<float*>(&s_cnt[slot]), ew[q]);
+          else
+            atomicAdd(&s_cnt[slot], 1u);
           atomicAdd(&s_sum0[slot], (double)er[q]);
           atomicAdd(&s_sum1[slot], (double)eg[q]);
           atomicAdd(&s_sum2[slot], (double)eb[q]);
@@ -509,12 +532,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       const uint32_t c = cnt[j];
       const unsigned long long k = s_key[s];
       if (kFused) {
-        const float alpha = blend_alpha(bp, c, old[j].c_old);
+        const float alpha = blend_alpha(bp, c, old[j].c_old, wtd);
         float L[3];
         load_state(old[j], bp.dtype, L[0], L[1], L[2]);
         // the new sample mean, rounded once from binary64
-        const float means[3] = {(float)(s_sum0[s] / (double)c), (float)(s_sum1[s] / (double)c),
-                                (float)(s_sum2[s] / (double)c)};
+        const double cd = wtd ? (double)__uint_as_float(c) : (double)c;
+        const float means[3] = {(float)(s_sum0[s] / cd), (float)(s_sum1[s] / cd), (float)(s_sum2[s] / cd)};
         float out[3];
         for (int ch = 0; ch < 3; ++ch) {
           const float m = means[ch];
@@ -524,7 +547,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
         Slot nw;
         nw.key = k;
-        nw.c_old = old[j].c_old + c;
+        nw.c_old = counter_add(old[j].c_old, c, wtd);
         nw.pad = 0;
         nw.L[0] = enc[0];
         nw.L[1] = enc[1];
@@ -543,7 +566,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         }
       } else {
         Acc a = acc_old[j];
-        a.n += c;
+        a.n = counter_add(a.n, c, wtd);
         a.s[0] += (float)s_sum0[s];
         a.s[1] += (float)s_sum1[s];
         a.s[2] += (float)s_sum2[s];
@@ -746,14 +769,31 @@ static bool partition_ok(const TableView& tv, const PartView& pv, uint64_t n) {
          bin_per_ok(pv.tile / kBinThreads) && (1u << (tv.log2_slots - tv.part_log2)) <= kTouchEntries;
 }
 
-template <uint32_t kPer, bool kFp>
+template <uint32_t kPer, uint32_t kX>
 static hipError_t launch_bin_t(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
                                const PartView& pv, size_t shm, uint32_t ntiles, hipStream_t s) {
   static LdsLimit lim;  // one per instantiation
-  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin<kPer, kFp>), shm, &lim);
+  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin<kPer, kX>), shm, &lim);
   if (e != hipSuccess) return e;
-  k_bin<kPer, kFp><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
+  k_bin<kPer, kX><<<ntiles, kBinThreads, shm, s>>>(rec, n, kp, tv, pv);
   return hipGetLastError();
+}
+
+template <uint32_t kPer>
+static hipError_t launch_bin_x(uint32_t x, const RecPtrs& rec, uint64_t n, const KeyParams& kp,
+                               const TableView& tv, const PartView& pv, size_t shm, uint32_t ntiles,
+                               hipStream_t s) {
+  switch (x) {
+    case 0: return launch_bin_t<kPer, 0>(rec, n, kp, tv, pv, shm, ntiles, s);
+    case kXFootprint: return launch_bin_t<kPer, kXFootprint>(rec, n, kp, tv, pv, shm, ntiles, s);
+    case kXWeight: return launch_bin_t<kPer, kXWeight>(rec, n, kp, tv, pv, shm, ntiles, s);
+    default: return launch_bin_t<kPer, kXFootprint | kXWeight>(rec, n, kp, tv, pv, shm, ntiles, s);
+  }
+}
+
+// What a launch's records carry (kX bits); weights need the staging array.
+static uint32_t record_extras(const RecPtrs& rec) {
+  return (rec.footprint ? kXFootprint : 0u) | (rec.weight ? kXWeight : 0u);
 }
 
 hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
@@ -764,15 +804,11 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
   const uint32_t per = pv.tile / kBinThreads;
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = bin_lds(P, per);
-  const bool fp = rec.footprint != nullptr;
-  if (per == 8)
-    return fp ? launch_bin_t<8, true>(rec, n, kp, tv, pv, shm, ntiles, s)
-              : launch_bin_t<8, false>(rec, n, kp, tv, pv, shm, ntiles, s);
-  if (per == 12)
-    return fp ? launch_bin_t<12, true>(rec, n, kp, tv, pv, shm, ntiles, s)
-              : launch_bin_t<12, false>(rec, n, kp, tv, pv, shm, ntiles, s);
-  return fp ? launch_bin_t<16, true>(rec, n, kp, tv, pv, shm, ntiles, s)
-            : launch_bin_t<16, false>(rec, n, kp, tv, pv, shm, ntiles, s);
+  const uint32_t x = record_extras(rec);
+  if ((x & kXWeight) && (!pv.stage_w || !weighted(tv))) return hipErrorInvalidValue;
+  if (per == 8) return launch_bin_x<8>(x, rec, n, kp, tv, pv, shm, ntiles, s);
+  if (per == 12) return launch_bin_x<12>(x, rec, n, kp, tv, pv, shm, ntiles, s);
+  return launch_bin_x<16>(x, rec, n, kp, tv, pv, shm, ntiles, s);
 }
 
 hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, const BlendParams* fuse,
@@ -855,15 +891,28 @@ __global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const Bat
   transpose_body(S.pv, P, S.ntiles, local % gx, local / gx);
 }
 
-template <uint32_t kPer, bool kFp>
+// kX: the union of the sessions' record extras; each session runs the body
+// of its own.
+template <uint32_t kPer, uint32_t kW, uint32_t kFpAllowed>
+__device__ __forceinline__ void bin_session(const BatchSession& S, uint32_t local) {
+  if (kFpAllowed && S.rec.footprint)
+    bin_body<kPer, kW | kXFootprint>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+  else
+    bin_body<kPer, kW>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+}
+
+template <uint32_t kPer, uint32_t kX>
 __global__ void __launch_bounds__(kBinThreads) k_bin_batch(const BatchSession* ss, uint32_t k) {
   const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 0)];
   const uint32_t local = blockIdx.x - S.tile_begin;
   if (local >= S.ntiles) return;
-  if (kFp && S.rec.footprint)
-    bin_body<kPer, true>(S.rec, S.n, S.kp, S.tv, S.pv, local);
-  else
-    bin_body<kPer, false>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+  if constexpr ((kX & kXWeight) != 0) {
+    if (S.rec.weight) {
+      bin_session<kPer, kXWeight, kX & kXFootprint>(S, local);
+      return;
+    }
+  }
+  bin_session<kPer, 0, kX & kXFootprint>(S, local);
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, uint32_t k) {
@@ -893,21 +942,32 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
   if (S.found) S.found[i] = hit;
 }
 
-template <uint32_t kPer, bool kFp>
+template <uint32_t kPer, uint32_t kX>
 static hipError_t launch_bin_batch_t(const BatchSession* d_ss, uint32_t k, uint32_t tiles, size_t lds,
                                      hipStream_t s) {
   static LdsLimit lim;  // one per instantiation
-  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin_batch<kPer, kFp>), lds, &lim);
+  hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin_batch<kPer, kX>), lds, &lim);
   if (e != hipSuccess) return e;
-  k_bin_batch<kPer, kFp><<<tiles, kBinThreads, lds, s>>>(d_ss, k);
+  k_bin_batch<kPer, kX><<<tiles, kBinThreads, lds, s>>>(d_ss, k);
   return hipGetLastError();
+}
+
+template <uint32_t kPer>
+static hipError_t launch_bin_batch_x(uint32_t x, const BatchSession* d_ss, uint32_t k, uint32_t tiles,
+                                     size_t lds, hipStream_t s) {
+  switch (x) {
+    case 0: return launch_bin_batch_t<kPer, 0>(d_ss, k, tiles, lds, s);
+    case kXFootprint: return launch_bin_batch_t<kPer, kXFootprint>(d_ss, k, tiles, lds, s);
+    case kXWeight: return launch_bin_batch_t<kPer, kXWeight>(d_ss, k, tiles, lds, s);
+    default: return launch_bin_batch_t<kPer, kXFootprint | kXWeight>(d_ss, k, tiles, lds, s);
+  }
 }
 
 hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
   if (k == 0) return hipSuccess;
   uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   size_t lds_b = 0, lds_m = 0, lds_q = 0;
-  bool fp = false;  // any session's records carry footprints
+  uint32_t x = 0;  // what any session's records carry
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
     const BatchSession& S = h_ss[i];
@@ -925,19 +985,18 @@ hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint
       if (S.nq != S.n || S.nqblk != S.ntiles) return hipErrorInvalidValue;
       lds_q = unstage_lds(S.pv.tile);
     }
-    fp = fp || S.rec.footprint != nullptr;
+    const uint32_t xs = record_extras(S.rec);
+    if ((xs & kXWeight) && (!S.pv.stage_w || !weighted(S.tv))) return hipErrorInvalidValue;
+    x |= xs;
     tiles += S.ntiles;
     parts += (S.nparts + 7u) & ~7u;
     qblks += S.nqblk;
     trans += S.ntrans;
   }
   static LdsLimit lim_m, lim_q;
-  hipError_t e = fp ? (per == 8    ? launch_bin_batch_t<8, true>(d_ss, k, tiles, lds_b, s)
-                       : per == 12 ? launch_bin_batch_t<12, true>(d_ss, k, tiles, lds_b, s)
-                                   : launch_bin_batch_t<16, true>(d_ss, k, tiles, lds_b, s))
-                    : (per == 8    ? launch_bin_batch_t<8, false>(d_ss, k, tiles, lds_b, s)
-                       : per == 12 ? launch_bin_batch_t<12, false>(d_ss, k, tiles, lds_b, s)
-                                   : launch_bin_batch_t<16, false>(d_ss, k, tiles, lds_b, s));
+  hipError_t e = per == 8    ? launch_bin_batch_x<8>(x, d_ss, k, tiles, lds_b, s)
+                  : per == 12 ? launch_bin_batch_x<12>(x, d_ss, k, tiles, lds_b, s)
+                              : launch_bin_batch_x<16>(x, d_ss, k, tiles, lds_b, s);
   if (e != hipSuccess) return e;
   e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
   if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_query_batch), lds_q, &lim_q);
