@@ -209,3 +209,50 @@ def test_weights_need_a_weighted_table(env):
         t.iterate(to_device(rec))
     with pytest.raises(psf.PsfError):
         psf.Table(**wl["table"], weighted=2)
+
+
+@pytest.mark.parametrize("dtype_name,tol", [("F16", 2.5e-3), ("BF16", 2.0e-2)])
+def test_weighted_reduced_precision_state(env, dtype_name, tol):
+    """Weighted counters with a 16-bit approximant: keys exact, counters as
+    for FP32 state, the approximant within the storage format's error."""
+    import oracle
+    torch, psf = env
+    wl, _ = _tiny(0)
+    cfg = dict(wl["table"], weighted=1)
+    orc = oracle.Oracle(**cfg)
+    t = psf.Table(**cfg, insert_mode=2, state_dtype=getattr(psf, f"PSF_STATE_{dtype_name}"))
+    for it in range(wl["iterations"]):
+        _, rec = _tiny(it)
+        rec["weight"] = _weights(len(rec["px"]), it)
+        t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+    torch.cuda.synchronize()
+    g, o = t.export(), orc.export()
+    assert np.array_equal(g["keys"], o["keys"])
+    assert rel_err(g["c_old"], o["c_old"]).max() <= RTOL_F32
+    assert rel_err(g["L"], o["L"]).max() <= tol
+
+
+@pytest.mark.parametrize("insert_mode", [1, 2])
+def test_weighted_progressive_step(env, insert_mode):
+    """The progressive solver step on a weighted table: each vertex's
+    sample carries its MIS weight into the counters (closed furnace)."""
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    cfg = dict(W.furnace_table(), weighted=1)
+    t = psf.Table(**dict(cfg, insert_mode=insert_mode))
+    o = oracle.Oracle(**cfg)
+
+    def dev3(arrs):
+        return tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs)
+
+    for it in range(12):
+        x, nx, tp, em = W.furnace_paths(2048, 2, it)
+        x = dict(x, weight=_weights(len(x["px"]), it, bad=False))
+        want = oracle.progressive_step(o, x, nx, tp, em)
+        got = t.progressive_step(to_device(x), to_device(nx), dev3(tp), dev3(em))
+        torch.cuda.synchronize()
+        assert rel_err(got.cpu().numpy(), want).max() <= RTOL_F32, it
+    _compare(t, o, "progressive")
