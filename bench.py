@@ -321,6 +321,47 @@ def form_progressive(torch, psf, W, iters=16, paths=921600, verts=4):
     return res
 
 
+def form_weighted(torch, psf, W, iters=16):
+    """MIS-weighted counters (Eq. 5-6 with w != 1): the plain workload's fused
+    iteration on a weighted table whose records carry balance-heuristic
+    weights (10% of them 0: a technique the field leaves out), beside the
+    same frames on an unweighted table; per-kernel averages from HIP events."""
+    wl = W.plain()
+    sc = W.make_scene(wl)
+    n = W.records_per_iteration(wl)
+    frames = []
+    for i in range(2):
+        rec = dict(sc.generate(wl["gen"], i))
+        rec["weight"] = W.mis_weights(n, seed=40 + i, excluded=0.1)
+        frames.append(_dev(rec, torch))
+    plain = [{k: v for k, v in f.items() if k != "weight"} for f in frames]
+    res = {"workload": wl["name"], "records_per_iteration": n, "params": tuned(wl["name"]),
+           "weights": "balance heuristic of two lognormal(0, 1) densities, 10% zero"}
+    for name, weighted, fr in (("weighted", 1, frames), ("unweighted", 0, plain)):
+        t = psf.Table(**dict(with_params(wl["table"], tuned(wl["name"]), psf.PSF_FLAG_TIMING),
+                             max_batch=n, weighted=weighted))
+        o = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        f = torch.empty(n, dtype=torch.uint8, device="cuda")
+        for i in range(4):
+            t.iterate(fr[i % 2], out=o, found=f)
+        torch.cuda.synchronize()
+        t.kernel_times(reset=True)
+        t0 = time.perf_counter()
+        for k in range(iters):
+            t.iterate(fr[k % 2], out=o, found=f)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = {k: round(v[1] / max(1, v[0]), 5) for k, v in t.kernel_times().items()}
+        st = t.stats()
+        res[name] = {"records_per_s": round(n * iters / el, 1), "ms_per_iter": round(el / iters * 1e3, 4),
+                     "kernels_avg_ms": kt, "skipped_per_iter": st["skipped"] // (iters + 4),
+                     "dropped": st["dropped"]}
+        t.close()
+    res["note"] = ("per-kernel events add a little to ms_per_iter; error vs the binary64 oracle is "
+                   "asserted in tests/test_gpu_weights.py")
+    return res
+
+
 def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     """Poisson arrivals at 20/s, resolutions lognormal around 720p, 32-128
     iterations each, 1 spp, 4 vertices; continuous batching under an HBM
@@ -393,9 +434,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
-    ap.add_argument("--forms", default="precision,batched,serving,estimate,progressive",
+    ap.add_argument("--forms", default="precision,batched,serving,estimate,progressive,weighted",
                     help="comma list of extra forms to measure (precision,batched,serving,estimate,"
-                         "progressive) or ''")
+                         "progressive,weighted) or ''")
     ap.add_argument("--untuned", action="store_true",
                     help="library default launch parameters instead of the recorded tuned ones")
     ap.add_argument("--copy-calib", action="store_true",
@@ -549,7 +590,7 @@ def main():
     forms = {}
     for name in [f for f in args.forms.split(",") if f]:
         fn = {"precision": form_precision, "batched": form_batched, "serving": form_serving,
-              "estimate": form_estimate, "progressive": form_progressive}[name]
+              "estimate": form_estimate, "progressive": form_progressive, "weighted": form_weighted}[name]
         print(f"# measuring form {name}", file=sys.stderr, flush=True)
         forms[name] = fn(torch, psf, W)
         torch.cuda.empty_cache()

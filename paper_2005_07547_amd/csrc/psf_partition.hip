@@ -110,7 +110,6 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   uint64_t key[kPer];
   uint32_t pos[kPer];  // partition << 16 | rank, then the slot in the sorted tile; ~0 if unused
   float rgb[kPer][3];
-  float wt[kPer];
   uint32_t n_skip = 0, n_ovf = 0;
   const bool hr = rec.rough != nullptr;
   // Every load is unconditional (indices past the end are clamped, absent
@@ -169,7 +168,6 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       rgb[j][0] = kW ? f[q][9] * fw[q] : f[q][9];
       rgb[j][1] = kW ? f[q][10] * fw[q] : f[q][10];
       rgb[j][2] = kW ? f[q][11] * fw[q] : f[q][11];
-      wt[j] = fw[q];
     }
   }
   // rare-event counters: one atomic per wave when non-zero
@@ -215,18 +213,22 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   float* dst = pv.stage_rgb + 3 * t0;
   for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
   if (kW) {
+    // the weights are read again rather than held across the sort (that
+    // would cost the pass a block per CU)
     __syncthreads();
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j)
-      if (pos[j] != ~0u) s_f[pos[j]] = wt[j];
+      if (pos[j] != ~0u) s_f[pos[j]] = rec.weight[t0 + (uint64_t)j * kBinThreads + tid];
     __syncthreads();
     for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_w[t0 + i] = s_f[i];
   }
 }
 
+// Two 512-thread blocks per CU need at most 128 VGPRs (four waves per SIMD);
+// the instantiations with footprints or weights would take a few more.
 template <uint32_t kPer, uint32_t kX>
-__global__ void __launch_bounds__(kBinThreads) k_bin(RecPtrs rec, uint64_t n, KeyParams kp,
-                                                     TableView tv, PartView pv) {
+__global__ void __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(kPer <= 12 ? 4 : 1)))
+k_bin(RecPtrs rec, uint64_t n, KeyParams kp, TableView tv, PartView pv) {
   bin_body<kPer, kX>(rec, n, kp, tv, pv, blockIdx.x);
 }
 
@@ -901,8 +903,11 @@ __device__ __forceinline__ void bin_session(const BatchSession& S, uint32_t loca
     bin_body<kPer, kW>(S.rec, S.n, S.kp, S.tv, S.pv, local);
 }
 
+// (the batch instantiations that carry several bodies would spill heavily
+// under the same cap)
 template <uint32_t kPer, uint32_t kX>
-__global__ void __launch_bounds__(kBinThreads) k_bin_batch(const BatchSession* ss, uint32_t k) {
+__global__ void __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(kPer <= 12 && kX == 0 ? 4 : 1)))
+k_bin_batch(const BatchSession* ss, uint32_t k) {
   const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 0)];
   const uint32_t local = blockIdx.x - S.tile_begin;
   if (local >= S.ntiles) return;
