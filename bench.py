@@ -90,7 +90,25 @@ def cpu_baseline(wl, rec, budget_s):
             break
     return {"value": n * done / el, "unit": "vertex records/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} whole iteration(s) (insert+update+query) of {n} records of the "
-                      f"{wl['name']} workload, single thread, {el:.1f} s"}
+                      f"{wl['name']} workload, single thread, {el:.1f} s",
+            "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def device_info(torch) -> dict:
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
+            "memory_gib": round(p.total_memory / 2 ** 30, 1)}
 
 
 def _dev(rec, torch):
@@ -424,6 +442,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--repeats", type=int, default=10,
+                    help="fresh-table repeats of `steps` iterations for p50/p99")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="plain", choices=["plain", "tiny", "precision"])
     ap.add_argument("--pool", type=int, default=8, help="distinct iteration buffers, cycled")
@@ -486,7 +506,7 @@ def main():
     params = tuned(wl["name"]) if args.insert_mode == psf.PSF_INSERT_AUTO else {}
     steps = args.steps
 
-    def timed_pass(flags, steps=steps):
+    def timed_pass(flags, steps=steps, warmup=args.warmup):
         """Warm up, then time exactly `steps` iterations of a fresh table
         (wall clock around the loop, HIP events around every step)."""
         table = psf.Table(**dict(with_params(wl["table"], params, flags), state_dtype=dtype_code,
@@ -501,7 +521,7 @@ def main():
             else:
                 table.iterate(b, out=out, found=found)
 
-        for i in range(args.warmup):
+        for i in range(warmup):
             step(i)
         torch.cuda.synchronize()
         if flags & psf.PSF_FLAG_TIMING:
@@ -513,7 +533,7 @@ def main():
         t0 = time.perf_counter()
         for k in range(steps):
             ev[k][0].record()
-            step(args.warmup + k)
+            step(warmup + k)
             ev[k][1].record()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
@@ -528,6 +548,10 @@ def main():
     # with HIP events on the library's stream for the per-kernel times and
     # the roofline
     elapsed, iter_ms, st0, st1, _ = timed_pass(0)
+    # per-iteration latency: every iteration of `repeats` runs, each on a
+    # fresh table (its first frames included)
+    lat = [iter_ms] + [timed_pass(0, warmup=0)[1] for _ in range(max(0, args.repeats - 1))]
+    lat = np.concatenate(lat)
     kt, inst_ms, probes = {}, None, None
     if not args.no_timing:
         el2, _, _, _, kt = timed_pass(psf.PSF_FLAG_TIMING)
@@ -572,8 +596,10 @@ def main():
                    "log2_slots": wl["table"]["log2_slots"], "iterations_timed": steps,
                    "mode": "split" if args.split else "psf_iterate",
                    "insert_mode": args.insert_mode, "pool_buffers": pool, "params": params},
-        "p50_iter_ms": round(float(np.percentile(iter_ms, 50)), 4),
-        "p99_iter_ms": round(float(np.percentile(iter_ms, 99)), 4),
+        "p50_iter_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_iter_ms": round(float(np.percentile(lat, 99)), 4),
+        "latency_sample": f"{lat.size} iterations: {max(1, args.repeats)} fresh-table runs of {steps} "
+                          "(the first run after warm-up iterations)",
         "iteration_hbm_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
         "cells_touched_per_iteration": int(touched),
         "occupancy": round(st1["occupied"] / (1 << wl["table"]["log2_slots"]), 4),
@@ -582,6 +608,7 @@ def main():
         "instrumented_ms_per_step": inst_ms,
         "probe_hist": probes,
         "roofline": roofline,
+        "device": device_info(torch),
     }
     if not args.no_graph and not args.split:
         result["graph_replay"] = graph_replay(torch, psf, wl, bufs, out, found, args.steps, n, params)
