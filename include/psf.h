@@ -219,8 +219,12 @@ size_t psf_table_bytes(const psf_config* cfg);
 psf_status psf_create_table(const psf_config* cfg, void* device_buffer, size_t buffer_bytes,
                             psf_stream stream, psf_table** out);
 
-/* Synchronises the table's last stream and frees what the library
- * allocated.  NULL is a no-op. */
+/* Frees what the library allocated.  When the library allocated the
+ * table's device memory it first synchronises the table's last stream.  A
+ * caller-owned device_buffer is not waited for: work already enqueued on the
+ * table's stream still uses it, so the caller reuses or frees it only in
+ * that stream's order (or after synchronising), as with any stream-ordered
+ * allocation.  NULL is a no-op. */
 psf_status psf_destroy(psf_table* t);
 
 /* Scatter n records into the table (Eq. 5-6 accumulation; Algorithm 1's

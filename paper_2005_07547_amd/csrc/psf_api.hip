@@ -391,7 +391,9 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
 
 PSF_API psf_status psf_destroy(psf_table* t) {
   if (!t) return PSF_OK;
-  hipError_t e = hipStreamSynchronize(t->last);
+  // only memory the library frees needs the stream drained first (a pending
+  // timing event is released by the runtime once it completes)
+  hipError_t e = t->owns ? hipStreamSynchronize(t->last) : hipSuccess;
   hipError_t f = hipSuccess;
   if (t->owns) f = hipFree(t->base);
   if (t->timer) {
@@ -659,9 +661,17 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
   return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
 }
 
+// One allocation each side: the per-pass first blocks of the sessions
+// (4 x cap words, padded to 256 bytes), then the session descriptors, so a
+// launch uploads both with one copy.
 struct psf_batch {
   uint32_t cap = 0;
-  psf::BatchSession* host = nullptr;  // pinned
+  size_t begins_bytes = 0;
+  void* host_raw = nullptr;  // pinned
+  void* dev_raw = nullptr;
+  uint32_t* hbeg = nullptr;
+  psf::BatchSession* host = nullptr;
+  uint32_t* dbeg = nullptr;
   psf::BatchSession* dev = nullptr;
   hipEvent_t copied = nullptr;
   bool in_flight = false;
@@ -674,13 +684,20 @@ PSF_API psf_status psf_batch_create(uint32_t max_sessions, psf_batch** out) {
   psf_batch* b = new (std::nothrow) psf_batch();
   if (!b) return fail(PSF_OUT_OF_MEMORY, "host allocation failed");
   b->cap = max_sessions;
-  const size_t bytes = sizeof(psf::BatchSession) * max_sessions;
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->host), bytes, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->dev), bytes);
+  b->begins_bytes = align_up((size_t)4 * max_sessions * sizeof(uint32_t), 256);
+  const size_t bytes = b->begins_bytes + sizeof(psf::BatchSession) * max_sessions;
+  hipError_t e = hipHostMalloc(&b->host_raw, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&b->dev_raw, bytes);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    b->hbeg = static_cast<uint32_t*>(b->host_raw);
+    b->host = reinterpret_cast<psf::BatchSession*>(static_cast<char*>(b->host_raw) + b->begins_bytes);
+    b->dbeg = static_cast<uint32_t*>(b->dev_raw);
+    b->dev = reinterpret_cast<psf::BatchSession*>(static_cast<char*>(b->dev_raw) + b->begins_bytes);
+  }
   if (e != hipSuccess) {
-    if (b->host) (void)hipHostFree(b->host);
-    if (b->dev) (void)hipFree(b->dev);
+    if (b->host_raw) (void)hipHostFree(b->host_raw);
+    if (b->dev_raw) (void)hipFree(b->dev_raw);
     delete b;
     (void)hipGetLastError();
     return fail(PSF_OUT_OF_MEMORY, std::string("batch context: ") + hipGetErrorString(e));
@@ -693,8 +710,8 @@ PSF_API psf_status psf_batch_destroy(psf_batch* b) {
   if (!b) return PSF_OK;
   hipError_t e = b->in_flight ? hipEventSynchronize(b->copied) : hipSuccess;
   (void)hipEventDestroy(b->copied);
-  (void)hipHostFree(b->host);
-  (void)hipFree(b->dev);
+  (void)hipHostFree(b->host_raw);
+  (void)hipFree(b->dev_raw);
   delete b;
   return e == hipSuccess ? PSF_OK : hip_fail(e, "batch destroy");
 }
@@ -768,17 +785,22 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
     d.ntrans = d.pv.runs_t ? psf::transpose_blocks(d.ntiles, d.nparts) : 0u;
     d.qblk_begin = qblks;
     d.nqblk = d.fused_query ? d.ntiles : (uint32_t)((ss.nq + psf::kQueryBlock - 1) / psf::kQueryBlock);
+    b->hbeg[j] = d.tile_begin;
+    b->hbeg[b->cap + j] = d.part_begin;
+    b->hbeg[2 * b->cap + j] = d.qblk_begin;
+    b->hbeg[3 * b->cap + j] = d.trans_begin;
     tiles += d.ntiles;
     parts += (d.nparts + 7u) & ~7u;
     trans += d.ntrans;
     qblks += d.nqblk;
   }
   const uint32_t m = (uint32_t)batch.size();
-  e = hipMemcpyAsync(b->dev, b->host, sizeof(psf::BatchSession) * m, hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(b->dev_raw, b->host_raw, b->begins_bytes + sizeof(psf::BatchSession) * m,
+                     hipMemcpyHostToDevice, s);
   if (e == hipSuccess && cap == hipStreamCaptureStatusNone) e = hipEventRecord(b->copied, s);
   if (e != hipSuccess) return hip_fail(e, "batch descriptor copy");
   b->in_flight = cap == hipStreamCaptureStatusNone;
-  e = psf::launch_batch(b->dev, b->host, m, s);
+  e = psf::launch_batch(b->dev, b->dbeg, b->hbeg, b->cap, b->host, m, s);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   for (uint32_t j = 0; j < m; ++j) {
     const psf_session& ss = sessions[batch[j]];

@@ -123,11 +123,16 @@ struct BatchSession {
   int32_t pad;
 };
 
-// Launch the three batch kernels for k sessions (all partition-capable, no
+// Launch the batch kernels for k sessions (all partition-capable, no
 // pending samples, the same binning width); d_sessions is device memory.
-hipError_t launch_batch(const BatchSession* d_sessions, const BatchSession* h_sessions, uint32_t k,
-                        hipStream_t s);
-constexpr uint32_t kQueryBlock = 256;
+// begins (device d_begins, host mirror h_begins) holds, per pass, each
+// session's first block: [0, k) binning tiles, [stride, stride + k) merge
+// partitions, [2 stride, ...) query blocks, [3 stride, ...) transpose blocks.
+hipError_t launch_batch(const BatchSession* d_sessions, const uint32_t* d_begins, const uint32_t* h_begins,
+                        uint32_t stride, const BatchSession* h_sessions, uint32_t k, hipStream_t s);
+// Threads of a batch query block: the lookup of kQueryBlock queries, or the
+// unstage of one fused session's tile (as wide as the single-table unstage).
+constexpr uint32_t kQueryBlock = 512;
 hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);

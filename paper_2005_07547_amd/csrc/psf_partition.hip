@@ -867,25 +867,24 @@ hipError_t launch_unstage(uint64_t n, const TableView& tv, const PartView& pv, f
 
 // ------------------------------------------------------------------ batched sessions
 // One launch per pass covers every session: a block finds its session by
-// its index among the sessions' block ranges (few sessions: a short scan of
-// uniform values) and runs the single-table body with the session's views.
-__device__ __forceinline__ uint32_t find_session(const BatchSession* ss, uint32_t k, uint32_t b,
-                                                 int which) {
-  uint32_t s = 0;
-  while (s + 1 < k) {
-    const BatchSession& nx = ss[s + 1];
-    const uint32_t begin = which == 0   ? nx.tile_begin
-                           : which == 1 ? nx.part_begin
-                           : which == 2 ? nx.qblk_begin
-                                        : nx.trans_begin;
-    if (begin > b) break;
-    ++s;
+// its index among the sessions' block ranges and runs the single-table body
+// with the session's views.  begins[0..k) holds each session's first block
+// of the pass (non-decreasing, begins[0] = 0); the block's session is the
+// last one starting at or before it: one coalesced load and a ballot per 64
+// sessions (a scan through the descriptors would cost a dependent load per
+// session).  Called by whole waves; the result is wave-uniform.
+__device__ __forceinline__ uint32_t find_session(const uint32_t* begins, uint32_t k, uint32_t b) {
+  uint32_t count = 0;
+  for (uint32_t c = 0; c < k; c += 64) {
+    const uint32_t i = c + __lane_id();
+    count += (uint32_t)__popcll(__ballot(i < k && begins[i] <= b));
   }
-  return s;
+  return count - 1;
 }
 
-__global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const BatchSession* ss, uint32_t k) {
-  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 3)];
+__global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const BatchSession* ss, const uint32_t* bg,
+                                                                       uint32_t k) {
+  const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.trans_begin;
   if (local >= S.ntrans || !S.pv.runs_t) return;
   const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
@@ -907,8 +906,8 @@ __device__ __forceinline__ void bin_session(const BatchSession& S, uint32_t loca
 // under the same cap)
 template <uint32_t kPer, uint32_t kX>
 __global__ void __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(kPer <= 12 && kX == 0 ? 4 : 1)))
-k_bin_batch(const BatchSession* ss, uint32_t k) {
-  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 0)];
+k_bin_batch(const BatchSession* ss, const uint32_t* bg, uint32_t k) {
+  const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.tile_begin;
   if (local >= S.ntiles) return;
   if constexpr ((kX & kXWeight) != 0) {
@@ -920,8 +919,9 @@ k_bin_batch(const BatchSession* ss, uint32_t k) {
   bin_session<kPer, 0, kX & kXFootprint>(S, local);
 }
 
-__global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, uint32_t k) {
-  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 1)];
+__global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, const uint32_t* bg,
+                                                                uint32_t k) {
+  const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.part_begin;
   if (local >= S.nparts) return;
   merge_body<true>(S.tv, S.pv, S.ntiles, S.bp, local, S.fused_query != 0);
@@ -929,8 +929,9 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSessio
 
 // A session whose queries are its records takes one unstage block per tile;
 // any other session one lookup block per kQueryBlock queries.
-__global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession* ss, uint32_t k) {
-  const BatchSession& S = ss[find_session(ss, k, blockIdx.x, 2)];
+__global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession* ss, const uint32_t* bg,
+                                                              uint32_t k) {
+  const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.qblk_begin;
   if (S.fused_query) {
     if (local < S.ntiles)
@@ -948,34 +949,39 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
 }
 
 template <uint32_t kPer, uint32_t kX>
-static hipError_t launch_bin_batch_t(const BatchSession* d_ss, uint32_t k, uint32_t tiles, size_t lds,
-                                     hipStream_t s) {
+static hipError_t launch_bin_batch_t(const BatchSession* d_ss, const uint32_t* bg, uint32_t k, uint32_t tiles,
+                                     size_t lds, hipStream_t s) {
   static LdsLimit lim;  // one per instantiation
   hipError_t e = lds_limit(reinterpret_cast<const void*>(&k_bin_batch<kPer, kX>), lds, &lim);
   if (e != hipSuccess) return e;
-  k_bin_batch<kPer, kX><<<tiles, kBinThreads, lds, s>>>(d_ss, k);
+  k_bin_batch<kPer, kX><<<tiles, kBinThreads, lds, s>>>(d_ss, bg, k);
   return hipGetLastError();
 }
 
 template <uint32_t kPer>
-static hipError_t launch_bin_batch_x(uint32_t x, const BatchSession* d_ss, uint32_t k, uint32_t tiles,
-                                     size_t lds, hipStream_t s) {
+static hipError_t launch_bin_batch_x(uint32_t x, const BatchSession* d_ss, const uint32_t* bg, uint32_t k,
+                                     uint32_t tiles, size_t lds, hipStream_t s) {
   switch (x) {
-    case 0: return launch_bin_batch_t<kPer, 0>(d_ss, k, tiles, lds, s);
-    case kXFootprint: return launch_bin_batch_t<kPer, kXFootprint>(d_ss, k, tiles, lds, s);
-    case kXWeight: return launch_bin_batch_t<kPer, kXWeight>(d_ss, k, tiles, lds, s);
-    default: return launch_bin_batch_t<kPer, kXFootprint | kXWeight>(d_ss, k, tiles, lds, s);
+    case 0: return launch_bin_batch_t<kPer, 0>(d_ss, bg, k, tiles, lds, s);
+    case kXFootprint: return launch_bin_batch_t<kPer, kXFootprint>(d_ss, bg, k, tiles, lds, s);
+    case kXWeight: return launch_bin_batch_t<kPer, kXWeight>(d_ss, bg, k, tiles, lds, s);
+    default: return launch_bin_batch_t<kPer, kXFootprint | kXWeight>(d_ss, bg, k, tiles, lds, s);
   }
 }
 
-hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
+hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, const uint32_t* h_begins,
+                        uint32_t stride, const BatchSession* h_ss, uint32_t k, hipStream_t s) {
   if (k == 0) return hipSuccess;
+  if (k > stride) return hipErrorInvalidValue;
   uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   size_t lds_b = 0, lds_m = 0, lds_q = 0;
   uint32_t x = 0;  // what any session's records carry
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
     const BatchSession& S = h_ss[i];
+    if (h_begins[i] != S.tile_begin || h_begins[stride + i] != S.part_begin ||
+        h_begins[2 * stride + i] != S.qblk_begin || h_begins[3 * stride + i] != S.trans_begin)
+      return hipErrorInvalidValue;
     if (S.n == 0 || !partition_ok(S.tv, S.pv, S.n) || S.pv.tile != h_ss[0].pv.tile ||
         S.tile_begin != tiles || S.part_begin != parts || S.qblk_begin != qblks || (S.part_begin & 7u) ||
         S.trans_begin != trans ||
@@ -999,19 +1005,23 @@ hipError_t launch_batch(const BatchSession* d_ss, const BatchSession* h_ss, uint
     trans += S.ntrans;
   }
   static LdsLimit lim_m, lim_q;
-  hipError_t e = per == 8    ? launch_bin_batch_x<8>(x, d_ss, k, tiles, lds_b, s)
-                  : per == 12 ? launch_bin_batch_x<12>(x, d_ss, k, tiles, lds_b, s)
-                              : launch_bin_batch_x<16>(x, d_ss, k, tiles, lds_b, s);
+  const uint32_t* bg_tile = d_begins;
+  const uint32_t* bg_part = d_begins + stride;
+  const uint32_t* bg_qblk = d_begins + 2 * stride;
+  const uint32_t* bg_trans = d_begins + 3 * stride;
+  hipError_t e = per == 8    ? launch_bin_batch_x<8>(x, d_ss, bg_tile, k, tiles, lds_b, s)
+                  : per == 12 ? launch_bin_batch_x<12>(x, d_ss, bg_tile, k, tiles, lds_b, s)
+                              : launch_bin_batch_x<16>(x, d_ss, bg_tile, k, tiles, lds_b, s);
   if (e != hipSuccess) return e;
   e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
   if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_query_batch), lds_q, &lim_q);
   if (e != hipSuccess) return e;
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (trans) k_transpose_batch<<<trans, kTransposeThreads, 0, s>>>(d_ss, k);
+  if (trans) k_transpose_batch<<<trans, kTransposeThreads, 0, s>>>(d_ss, bg_trans, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_merge_batch<<<parts, kMergeThreads, lds_m, s>>>(d_ss, k);
+  k_merge_batch<<<parts, kMergeThreads, lds_m, s>>>(d_ss, bg_part, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (qblks) k_query_batch<<<qblks, kQueryBlock, lds_q, s>>>(d_ss, k);
+  if (qblks) k_query_batch<<<qblks, kQueryBlock, lds_q, s>>>(d_ss, bg_qblk, k);
   return hipGetLastError();
 }
 

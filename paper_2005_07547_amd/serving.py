@@ -9,8 +9,13 @@ over time; at every tick the server
 2. runs one iteration (insert, temporal update, query) of every active
    session in a single batched call (``psf_iterate_batch``), so sessions that
    joined at different times share the device;
-3. retires sessions that have run all their iterations, freeing their memory
-   so that queued sessions can be admitted at the next tick.
+3. retires sessions that have run all their iterations.  Reading a retired
+   table's statistics and destroying it synchronise the stream, which would
+   leave the device idle while the host forms the next tick, so retired
+   sessions are flushed (statistics read, table closed, memory returned to
+   the budget) only when no tick is in flight, when a waiting session needs
+   their memory, or at the end of the run.  Until then their tables still
+   count against the budget.
 
 The host keeps two ticks in flight (the next tick is launched before the
 previous one is waited for), so host bookkeeping overlaps device work.  Per
@@ -71,6 +76,8 @@ class Server:
         self.ticks = 0
         self.records = 0
         self.dropped = 0
+        self.flushes = 0
+        self._retired = []  # finished sessions whose tables are not yet released
         self._torch = torch
 
     def _admit(self, s: SessionRequest, now: float):
@@ -83,12 +90,21 @@ class Server:
 
     def _retire(self, s: SessionRequest, now: float):
         s.finished_at = now
-        self.resident -= s.footprint
-        self.dropped += s.table.stats()["dropped"]
-        if not self.keep_tables:
-            s.table.close()
-            s.table = None
         s.out = s.found = None
+        self._retired.append(s)
+
+    def _flush(self):
+        """Release the retired sessions' tables (synchronises the stream)."""
+        if not self._retired:
+            return
+        for s in self._retired:
+            self.dropped += s.table.stats()["dropped"]
+            self.resident -= s.footprint
+            if not self.keep_tables:
+                s.table.close()
+                s.table = None
+        self._retired = []
+        self.flushes += 1
 
     def run(self, requests: list, time_limit: float = 600.0, on_tick=None):
         """Serve every request; returns a summary dict.  requests are sorted
@@ -110,6 +126,11 @@ class Server:
                 raise TimeoutError("serving run exceeded its time limit")
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.pop(0))
+            # retired tables are released when the device is idle anyway, or
+            # when the next waiting session needs their memory
+            if self._retired and (not inflight or (
+                    waiting and self.resident + waiting[0].footprint > self.budget)):
+                self._flush()
             # admission in arrival order while memory and slots allow
             while waiting and len(active) < self.max_active and \
                     self.resident + waiting[0].footprint <= self.budget:
@@ -150,6 +171,7 @@ class Server:
                     on_tick(self)
             elif not runnable and not inflight and not waiting and pending:
                 time.sleep(min(0.001, max(0.0, pending[0].arrival - now)))
+        self._flush()
         wall = time.perf_counter() - t0
         lat = sorted(x for s in finished for x in s.latencies_ms)
 
@@ -163,7 +185,7 @@ class Server:
             "wall_s": wall, "records_per_s": self.records / wall if wall > 0 else math.nan,
             "p50_iter_ms": pct(50), "p99_iter_ms": pct(99),
             "peak_active": self.peak_active, "peak_resident_bytes": self.peak_resident,
-            "dropped": self.dropped,
+            "dropped": self.dropped, "flushes": self.flushes,
             "mean_queue_s": sum(s.admitted_at - s.arrival for s in finished) / max(1, len(finished)),
         }
 
