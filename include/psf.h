@@ -74,7 +74,8 @@ enum { PSF_RESET_COUNTERS = 1u, PSF_RESET_CLEAR = 2u, PSF_RESET_STATS = 4u };
 
 /* Insert strategies (psf_config.insert_mode). */
 enum {
-  PSF_INSERT_AUTO = 0,        /* library choice */
+  PSF_INSERT_AUTO = 0,        /* library choice: partitioned when the table
+                                 has at most 8192 partitions, else direct */
   PSF_INSERT_DIRECT = 1,      /* wave-merged global CAS/atomics per record */
   PSF_INSERT_PARTITIONED = 2  /* bin by table partition, aggregate in LDS */
 };
@@ -138,7 +139,9 @@ typedef struct psf_config {
   uint32_t flags;            /* PSF_FLAG_* */
   int32_t insert_mode;       /* PSF_INSERT_* */
   uint32_t part_log2;        /* partitioned insert: log2 slots per partition
-                                (0 = default 11, else 8..12) */
+                                (0 = default: 11, or 12 for tables of 2^25
+                                slots; else 8..12).  A table of more than
+                                8192 partitions takes the direct strategy. */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M, at most 2^31); larger
                                 inserts are split */
@@ -322,7 +325,8 @@ psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint3
  * result equals the same session run alone through psf_iterate.  Sessions
  * that cannot join the batch (direct insert strategy, samples pending from
  * psf_insert_samples, n above the table's max_batch, a binning width
- * different from the first batchable session's) run through psf_iterate
+ * different from the first batchable session's, partitions wider than both
+ * 2^11 slots and the narrowest batchable session's) run through psf_iterate
  * first, on the same stream.  d_out_rgb (3*nq floats, SoA) and d_out_found
  * (nullable) as in psf_query; queries equal to the records (the same
  * arrays) are answered by the merge pass, as in psf_iterate. */

@@ -162,7 +162,11 @@ struct Layout {
 Layout layout_of(const psf_config& c) {
   Layout L;
   const uint64_t S = 1ull << c.log2_slots;
-  L.part_log2 = c.part_log2 ? c.part_log2 : kDefaultPartLog2;
+  // default partition width: 2^11 slots, wider for tables that would
+  // otherwise exceed the binning pass's partition count
+  uint32_t def = kDefaultPartLog2;
+  while (def < 12 && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kMaxPartitions) ++def;
+  L.part_log2 = c.part_log2 ? c.part_log2 : def;
   if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;
   const uint64_t P = 1ull << (c.log2_slots - L.part_log2);
   L.part = c.insert_mode != PSF_INSERT_DIRECT && P <= kMaxPartitions;
@@ -732,14 +736,25 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
       if (sessions[j].table == ss.table) return fail(PSF_INVALID_ARGUMENT, "a table appears twice in one batch");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // sessions that cannot join run alone first
+  // sessions that cannot join run alone first.  The merge launch sizes its
+  // LDS for the widest partitions in it, so a session whose partitions are
+  // wider than both the default and the narrowest candidate's runs alone
+  // rather than slowing every other session's merge blocks.
+  auto candidate = [&](const psf_session& ss) {
+    const psf_table* t = ss.table;
+    return ss.n > 0 && t->partitioned && !t->pending && ss.n <= t->pv.capacity;
+  };
+  uint32_t part_cap = 0;
+  for (uint32_t i = 0; i < k; ++i)
+    if (candidate(sessions[i]) && (part_cap == 0 || sessions[i].table->tv.part_log2 < part_cap))
+      part_cap = sessions[i].table->tv.part_log2;
+  if (part_cap < kDefaultPartLog2) part_cap = kDefaultPartLog2;
   uint32_t tile = 0;
   std::vector<uint32_t> batch;
   for (uint32_t i = 0; i < k; ++i) {
     const psf_session& ss = sessions[i];
     psf_table* t = ss.table;
-    const bool ok = ss.n > 0 && t->partitioned && !t->pending && ss.n <= t->pv.capacity &&
-                    (tile == 0 || t->pv.tile == tile);
+    const bool ok = candidate(ss) && t->tv.part_log2 <= part_cap && (tile == 0 || t->pv.tile == tile);
     if (ok) {
       tile = t->pv.tile;
       batch.push_back(i);

@@ -162,3 +162,26 @@ def test_batch_with_footprint_sessions(env):
         out, found = res[i]
         assert np.array_equal(found.cpu().numpy(), w_found)
         assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+
+
+def test_wide_partition_session_runs_alone_with_the_same_result(env):
+    """A session with 4096-slot partitions beside default ones leaves the
+    shared launch (it would widen every merge block's LDS) and still gets
+    the result it gets alone."""
+    torch, psf = env
+    ss = _sessions(3)
+    cfgs = [dict(wl["table"], part_log2=12 if i == 1 else 0) for i, (wl, _) in enumerate(ss)]
+    alone = [psf.Table(**c) for c in cfgs]
+    mixed = [psf.Table(**c) for c in cfgs]
+    batch = psf.Batch(4)
+    for it in range(2):
+        dev = [to_device(_frame(wl, sc, it)) for wl, sc in ss]
+        res_alone = [t.iterate(d) for t, d in zip(alone, dev)]
+        res_mix = batch.iterate(mixed, dev)
+        torch.cuda.synchronize()
+        for (oa, fa), (om, fm) in zip(res_alone, res_mix):
+            assert np.array_equal(fa.cpu().numpy(), fm.cpu().numpy())
+            assert rel_err(om.cpu().numpy(), oa.cpu().numpy()).max() <= RTOL_F32
+    for a, m in zip(alone, mixed):
+        ea, em = a.export(), m.export()
+        assert np.array_equal(ea["keys"], em["keys"]) and np.array_equal(ea["c_old"], em["c_old"])

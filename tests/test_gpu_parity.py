@@ -579,3 +579,24 @@ def test_multi_level_lookup(psf, torch_cuda):
         assert np.array_equal(level.cpu().numpy(), w_level), up
         assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, up
     assert int((w_level >= 2).sum()) > 0 and int((w_level == 0).sum()) < len(w_level)
+
+
+def test_large_table_default_partitions_stay_partitioned(psf, torch_cuda):
+    """A 2^25-slot table with the default partition width takes 4096-slot
+    partitions (at most 8192 of them), so the automatic strategy stays
+    partitioned; results match the oracle."""
+    wl, _ = _tiny(0)
+    cfg = dict(wl["table"], log2_slots=25)
+    orc = _oracle(cfg)
+    t = psf.Table(**cfg, flags=psf.PSF_FLAG_TIMING)
+    for it in range(3):
+        _, rec = _tiny(it)
+        out, found = t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+        torch_cuda.cuda.synchronize()
+        w_out, w_found = orc.query(rec)
+        assert np.array_equal(found.cpu().numpy(), w_found), it
+        assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, it
+    assert {"bin", "merge_blend"} <= set(t.kernel_times())
+    compare_cells(t.export(), orc.export(), RTOL_F32, "2^25 slots")
