@@ -614,9 +614,11 @@ PSF_API psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream
   if (st != PSF_OK) return st;
   std::memset(out, 0, sizeof *out);
   out->submitted = t->submitted;
-  out->skipped = d.skipped;
+  for (uint32_t l = 0; l < psf::kStatLanes; ++l) {
+    out->skipped += d.skipped[l][0];
+    out->coord_overflow += d.coord_overflow[l][0];
+  }
   out->dropped = d.dropped;
-  out->coord_overflow = d.coord_overflow;
   for (uint32_t i = 0; i < psf::kTouchEntries; ++i) {
     if (i < t->touch_entries) out->touched_last += bt[i].last;
     out->touched_total += bt[i].total;

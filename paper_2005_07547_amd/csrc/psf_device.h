@@ -42,15 +42,25 @@ struct alignas(16) Acc {
   float s[3];
 };
 
-// Device-resident counters of rare events (one atomic per wave or block
-// when non-zero).
+// Device-resident event counters (one atomic per wave or block when
+// non-zero).  Rejected samples are not always rare (a field that leaves a
+// sampling technique out rejects every sample of it), so the skip and
+// overflow counts are spread over kStatLanes counters a cache line apart,
+// picked by block index, and summed when the statistics are read: atomics
+// on one address serialise.
+constexpr uint32_t kStatLanes = 32;
 struct alignas(256) DevStats {
-  unsigned long long skipped;
   unsigned long long dropped;
-  unsigned long long coord_overflow;
   unsigned long long saturated;
   unsigned long long probe_hist[16];
+  unsigned long long pad[14];
+  unsigned long long skipped[kStatLanes][8];         // [lane][0] used
+  unsigned long long coord_overflow[kStatLanes][8];  // [lane][0] used
 };
+
+__device__ __forceinline__ unsigned long long* stat_lane(unsigned long long (*c)[8], uint32_t block) {
+  return &c[block % kStatLanes][0];
+}
 
 // Per-block count of blended cells, written by the block that owns the entry
 // (no shared counters on the hot path).

@@ -20,10 +20,11 @@ struct QryPtrs {
 // Partitioned-insert working buffers of one table.
 struct PartView {
   unsigned long long* stage_key;  // staged sample keys, grouped per tile by partition
-  float* stage_rgb;               // staged sample values (r, g, b triples; times the
-                                  // weight in a weighted table), same order
+  float* stage_rgb;               // staged sample values (r, g, b triples), same order
   float* stage_w;                 // staged weights, same order (null: this launch's
-                                  // records carry none, every weight 1)
+                                  // records carry none, every weight 1); the merge
+                                  // pass ignores a sample whose weight is not
+                                  // finite and > 0
   uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile
   uint32_t* runs_t;               // the same, transposed: [partition + 1][max_tiles]
                                   // (null: not transposed for this launch)

@@ -123,8 +123,8 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
     }
     skip = !valid;
   }
-  wave_count(&tv.stats->skipped, skip);
-  wave_count(&tv.stats->coord_overflow, valid && ovf);
+  wave_count(stat_lane(tv.stats->skipped, blockIdx.x), skip);
+  wave_count(stat_lane(tv.stats->coord_overflow, blockIdx.x), valid && ovf);
 
   // elect a leader lane per distinct key
   uint64_t pending = __ballot(valid);

@@ -87,9 +87,11 @@ __device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_
 // keys, then rgb triples), so that both global writes of the partition-
 // sorted tile are coalesced.
 // kX: what the records carry beyond the common fields, kXFootprint (their
-// level rule) and kXWeight (MIS weights: the staged values are w * rgb and
-// the weights are staged as well); separate instantiations keep the extra
-// loads and their registers out of the common case.
+// level rule) and kXWeight (MIS weights, staged beside the values, which
+// stay unweighted; a weight is read only by the staging pass, which also
+// counts the samples it rejects, and the merge pass applies it); separate
+// instantiations keep the extra loads and their registers out of the
+// common case.
 constexpr uint32_t kXFootprint = 1, kXWeight = 2;
 
 template <uint32_t kPer, uint32_t kX>
@@ -111,6 +113,10 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   uint32_t pos[kPer];  // partition << 16 | rank, then the slot in the sorted tile; ~0 if unused
   float rgb[kPer][3];
   uint32_t n_skip = 0, n_ovf = 0;
+  // with weights, two flags of a staged record ride in the top bits of its
+  // position (partition < 2^13 before the scan, position < 2^14 after it):
+  // staged for lookup only, and counted as a coordinate overflow
+  constexpr uint32_t kPosLookupOnly = 1u << 31, kPosOverflow = 1u << 30, kPosBits = kPosOverflow - 1;
   const bool hr = rec.rough != nullptr;
   // Every load is unconditional (indices past the end are clamped, absent
   // arrays alias the positions) so that a batch of records is a single
@@ -123,7 +129,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
 #pragma unroll
   for (uint32_t j0 = 0; j0 < kPer; j0 += kLoad) {
     float f[kLoad][13];
-    float fp[kLoad], fw[kLoad];
+    float fp[kLoad];
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint64_t i = t0 + (uint64_t)(j0 + q) * kBinThreads + tid;
@@ -142,7 +148,6 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       f[q][11] = rec.b[ic];
       f[q][12] = p_ro[ic];
       fp[q] = kFp ? rec.footprint[ic] : 0.0f;
-      fw[q] = kW ? rec.weight[ic] : 1.0f;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
@@ -154,8 +159,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       uint64_t k;
       const bool kv = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
                                f[q][7], f[q][8], hr, f[q][12], kFp, fp[q], k, ovf);
-      const bool sv = finite3(f[q][9], f[q][10], f[q][11]) &&
-                      (!kW || (__builtin_isfinite(fw[q]) && fw[q] > 0.0f));
+      const bool sv = finite3(f[q][9], f[q][10], f[q][11]);
       if (!(kv && sv)) ++n_skip;
       // a record whose sample is rejected but whose key is valid is still a
       // query vertex: with the fused query it is staged for lookup only
@@ -165,62 +169,81 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       const uint32_t rank = atomicAdd(&s_hist[p], 1u);
       key[j] = sv ? k : k | kLookupOnlyBit;
       pos[j] = (p << 16) | rank;
-      rgb[j][0] = kW ? f[q][9] * fw[q] : f[q][9];
-      rgb[j][1] = kW ? f[q][10] * fw[q] : f[q][10];
-      rgb[j][2] = kW ? f[q][11] * fw[q] : f[q][11];
+      if (kW) pos[j] |= (sv ? 0u : kPosLookupOnly) | ((ovf && sv) ? kPosOverflow : 0u);
+      rgb[j][0] = f[q][9];
+      rgb[j][1] = f[q][10];
+      rgb[j][2] = f[q][11];
     }
   }
-  // rare-event counters: one atomic per wave when non-zero
-  for (int off = 32; off > 0; off >>= 1) {
-    n_skip += __shfl_xor(n_skip, off);
-    n_ovf += __shfl_xor(n_ovf, off);
-  }
-  if (__lane_id() == 0) {
-    if (n_skip) atomicAdd(&tv.stats->skipped, (unsigned long long)n_skip);
-    if (n_ovf) atomicAdd(&tv.stats->coord_overflow, (unsigned long long)n_ovf);
-  }
+  // rare-event counters: one atomic per wave when non-zero (with weights,
+  // after the staging pass has judged them)
+  auto count_events = [&]() {
+    for (int off = 32; off > 0; off >>= 1) {
+      n_skip += __shfl_xor(n_skip, off);
+      n_ovf += __shfl_xor(n_ovf, off);
+    }
+    if (__lane_id() == 0) {
+      if (n_skip) atomicAdd(stat_lane(tv.stats->skipped, tile), (unsigned long long)n_skip);
+      if (n_ovf) atomicAdd(stat_lane(tv.stats->coord_overflow, tile), (unsigned long long)n_ovf);
+    }
+  };
+  if (!kW) count_events();
   __syncthreads();
   const uint32_t count = block_exclusive_scan<kBinThreads>(s_hist, P + 1, s_wave);
 
   uint32_t* offs = pv.runs + (uint64_t)tile * (P + 1);
   for (uint32_t p = tid; p <= P; p += kBinThreads) offs[p] = s_hist[p];
 #pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j)
-    if (pos[j] != ~0u) pos[j] = s_hist[pos[j] >> 16] + (pos[j] & 0xffffu);
+  for (uint32_t j = 0; j < kPer; ++j) {
+    if (pos[j] == ~0u) continue;
+    const uint32_t q = pos[j] & kPosBits;
+    pos[j] = (s_hist[q >> 16] + (q & 0xffffu)) | (pos[j] & ~kPosBits);
+  }
   if (pv.perm) {
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
       const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
-      if (i < n) pv.perm[i] = pos[j] != ~0u ? (uint16_t)pos[j] : kNoPos;
+      if (i < n) pv.perm[i] = pos[j] != ~0u ? (uint16_t)(pos[j] & kPosBits) : kNoPos;
     }
   }
   __syncthreads();  // the histogram is dead from here on; its LDS becomes staging
 
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j)
-    if (pos[j] != ~0u) s_k[pos[j]] = key[j];
+    if (pos[j] != ~0u) s_k[pos[j] & kPosBits] = key[j];
   __syncthreads();
   for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_key[t0 + i] = s_k[i];
   __syncthreads();
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j) {
     if (pos[j] == ~0u) continue;
-    s_f[3 * pos[j] + 0] = rgb[j][0];
-    s_f[3 * pos[j] + 1] = rgb[j][1];
-    s_f[3 * pos[j] + 2] = rgb[j][2];
+    const uint32_t o = 3 * (pos[j] & kPosBits);
+    s_f[o + 0] = rgb[j][0];
+    s_f[o + 1] = rgb[j][1];
+    s_f[o + 2] = rgb[j][2];
   }
   __syncthreads();
   float* dst = pv.stage_rgb + 3 * t0;
   for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
   if (kW) {
-    // the weights are read again rather than held across the sort (that
-    // would cost the pass a block per CU)
+    // The weights are first read here.  A staged sample whose weight is not
+    // finite and > 0 is rejected: counted as skipped (not as a coordinate
+    // overflow), and the merge pass, seeing the weight, does not accumulate
+    // it (with the fused query it is still looked up).
     __syncthreads();
 #pragma unroll
-    for (uint32_t j = 0; j < kPer; ++j)
-      if (pos[j] != ~0u) s_f[pos[j]] = rec.weight[t0 + (uint64_t)j * kBinThreads + tid];
+    for (uint32_t j = 0; j < kPer; ++j) {
+      if (pos[j] == ~0u) continue;
+      const float w = rec.weight[t0 + (uint64_t)j * kBinThreads + tid];
+      s_f[pos[j] & kPosBits] = w;
+      if (!(pos[j] & kPosLookupOnly) && !(__builtin_isfinite(w) && w > 0.0f)) {
+        ++n_skip;
+        n_ovf -= (pos[j] & kPosOverflow) ? 1u : 0u;
+      }
+    }
     __syncthreads();
     for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_w[t0 + i] = s_f[i];
+    count_events();
   }
 }
 
@@ -462,9 +485,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       uint32_t slot = ~0u;
-      const bool lookup_only = results && (ek[q] & kLookupOnlyBit) != 0;
+      // a staged weight that is not finite and > 0 rejects the sample: with
+      // the fused query the entry is only looked up, else it is ignored
+      const bool wbad = pv.stage_w && !(__builtin_isfinite(ew[q]) && ew[q] > 0.0f);
+      const bool lookup_only = results && ((ek[q] & kLookupOnlyBit) != 0 || wbad);
       if (lookup_only) slot = kLookupLater;
-      if (ev[q] && !lookup_only) {
+      if (ev[q] && !lookup_only && !wbad) {
         const unsigned long long key = ek[q];
         const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
         uint32_t i = 0;
@@ -485,9 +511,17 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
             atomicAdd(reinterpret_cast<float*>(&s_cnt[slot]), ew[q]);
           else
             atomicAdd(&s_cnt[slot], 1u);
-          atomicAdd(&s_sum0[slot], (double)er[q]);
-          atomicAdd(&s_sum1[slot], (double)eg[q]);
-          atomicAdd(&s_sum2[slot], (double)eb[q]);
+          if (pv.stage_w) {
+            // w * value exactly (binary64 holds the product of two binary32)
+            const double dw = (double)ew[q];
+            atomicAdd(&s_sum0[slot], (double)er[q] * dw);
+            atomicAdd(&s_sum1[slot], (double)eg[q] * dw);
+            atomicAdd(&s_sum2[slot], (double)eb[q] * dw);
+          } else {
+            atomicAdd(&s_sum0[slot], (double)er[q]);
+            atomicAdd(&s_sum1[slot], (double)eg[q]);
+            atomicAdd(&s_sum2[slot], (double)eb[q]);
+          }
         }
       }
       if (results) {
