@@ -902,7 +902,10 @@ hipError_t launch_unstage(uint64_t n, const TableView& tv, const PartView& pv, f
 // ------------------------------------------------------------------ batched sessions
 // One launch per pass covers every session: a block finds its session by
 // its index among the sessions' block ranges and runs the single-table body
-// with the session's views.  begins[0..k) holds each session's first block
+// with the session's views, copied out of the descriptor first (read in
+// place, the descriptor is global memory the body's stores might alias, so
+// its fields would be loaded again after every store: the batched merge ran
+// 15 % slower than the single-table one that way).  begins[0..k) holds each session's first block
 // of the pass (non-decreasing, begins[0] = 0); the block's session is the
 // last one starting at or before it: one coalesced load and a ballot per 64
 // sessions (a scan through the descriptors would cost a dependent load per
@@ -920,20 +923,27 @@ __global__ void __launch_bounds__(kTransposeThreads) k_transpose_batch(const Bat
                                                                        uint32_t k) {
   const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.trans_begin;
-  if (local >= S.ntrans || !S.pv.runs_t) return;
+  const PartView pv = S.pv;
+  if (local >= S.ntrans || !pv.runs_t) return;
   const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
-  const uint32_t gx = (S.ntiles + kTransposeDim - 1) / kTransposeDim;
-  transpose_body(S.pv, P, S.ntiles, local % gx, local / gx);
+  const uint32_t ntiles = S.ntiles;
+  const uint32_t gx = (ntiles + kTransposeDim - 1) / kTransposeDim;
+  transpose_body(pv, P, ntiles, local % gx, local / gx);
 }
 
 // kX: the union of the sessions' record extras; each session runs the body
 // of its own.
 template <uint32_t kPer, uint32_t kW, uint32_t kFpAllowed>
 __device__ __forceinline__ void bin_session(const BatchSession& S, uint32_t local) {
-  if (kFpAllowed && S.rec.footprint)
-    bin_body<kPer, kW | kXFootprint>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+  const RecPtrs rec = S.rec;
+  const KeyParams kp = S.kp;
+  const TableView tv = S.tv;
+  const PartView pv = S.pv;
+  const uint64_t n = S.n;
+  if (kFpAllowed && rec.footprint)
+    bin_body<kPer, kW | kXFootprint>(rec, n, kp, tv, pv, local);
   else
-    bin_body<kPer, kW>(S.rec, S.n, S.kp, S.tv, S.pv, local);
+    bin_body<kPer, kW>(rec, n, kp, tv, pv, local);
 }
 
 // (the batch instantiations that carry several bodies would spill heavily
@@ -958,7 +968,10 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSessio
   const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.part_begin;
   if (local >= S.nparts) return;
-  merge_body<true>(S.tv, S.pv, S.ntiles, S.bp, local, S.fused_query != 0);
+  const TableView tv = S.tv;
+  const PartView pv = S.pv;
+  const BlendParams bp = S.bp;
+  merge_body<true>(tv, pv, S.ntiles, bp, local, S.fused_query != 0);
 }
 
 // A session whose queries are its records takes one unstage block per tile;
@@ -967,19 +980,26 @@ __global__ void __launch_bounds__(kQueryBlock) k_query_batch(const BatchSession*
                                                               uint32_t k) {
   const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.qblk_begin;
+  float* out = S.out;
+  uint8_t* found = S.found;
   if (S.fused_query) {
+    const PartView pv = S.pv;
     if (local < S.ntiles)
-      unstage_body(S.pv, 1u << (S.tv.log2_slots - S.tv.part_log2), S.n, local, S.out, S.found);
+      unstage_body(pv, 1u << (S.tv.log2_slots - S.tv.part_log2), S.n, local, out, found);
     return;
   }
+  const uint64_t nq = S.nq;
   const uint64_t i = (uint64_t)local * kQueryBlock + threadIdx.x;
-  if (i >= S.nq) return;
+  if (i >= nq) return;
+  const TableView tv = S.tv;
+  const KeyParams kp = S.kp;
+  const QryPtrs q = S.q;
   float rgb[3];
-  const uint8_t hit = lookup_key(S.tv, S.bp.dtype, query_key(S.kp, S.q, i), rgb);
-  S.out[i] = rgb[0];
-  S.out[S.nq + i] = rgb[1];
-  S.out[2 * S.nq + i] = rgb[2];
-  if (S.found) S.found[i] = hit;
+  const uint8_t hit = lookup_key(tv, S.bp.dtype, query_key(kp, q, i), rgb);
+  out[i] = rgb[0];
+  out[nq + i] = rgb[1];
+  out[2 * nq + i] = rgb[2];
+  if (found) found[i] = hit;
 }
 
 template <uint32_t kPer, uint32_t kX>
