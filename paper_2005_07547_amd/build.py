@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libpsf.so")
-SOURCES = ["psf_api.hip", "psf_kernels.hip", "psf_partition.hip", "psf_batch.hip"]
+SOURCES = ["psf_api.hip", "psf_kernels.hip", "psf_partition.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
-            continue
+            raise FileNotFoundError(f"listed HIP source is missing: {path}")
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
         if verbose:
