@@ -63,8 +63,22 @@ enum { PSF_ALPHA_PAPER = 0, PSF_ALPHA_CONST = 1, PSF_ALPHA_LINEAR = 2 };
 
 /* Storage of the approximant.  The blend always runs in FP32 and the
  * accumulators are FP32; F16 and BF16 round to nearest even on store (F16
- * saturates at +-65504 and counts each saturation). */
-enum { PSF_STATE_F32 = 0, PSF_STATE_F16 = 1, PSF_STATE_BF16 = 2 };
+ * saturates at +-65504 and counts each saturation).  F16 and BF16 blend from
+ * the stored 16-bit value, so every frame re-rounds the state (the error
+ * grows to about u * T_max relative, u the format's unit roundoff).  F16_EF
+ * and BF16_EF store the same 16-bit approximant, which is what lookups,
+ * exports and estimators read, and also carry each channel's FP32 rounding
+ * residual in the slot (error feedback): the blend continues from the
+ * unrounded FP32 value, so a lookup sees one rounding (relative error
+ * <= u in the format's normal range).  The slot is 32 bytes in every
+ * format. */
+enum {
+  PSF_STATE_F32 = 0,
+  PSF_STATE_F16 = 1,
+  PSF_STATE_BF16 = 2,
+  PSF_STATE_F16_EF = 3,
+  PSF_STATE_BF16_EF = 4
+};
 
 /* psf_reset what-bits.  COUNTERS zeroes every cell's c_old (the global
  * counter reset of Sec. 2.4): cells keep their key but are not reported by

@@ -66,6 +66,19 @@ def _load():
     lib.orc_export.restype = u64
     lib.orc_export.argtypes = [vp, vp, vp, vp, vp, vp, u64]
     lib.orc_counters.argtypes = [vp, vp, vp, vp]
+    lib.orc_sharded_create.restype = vp
+    lib.orc_sharded_create.argtypes = [u32] + lib.orc_create.argtypes
+    lib.orc_sharded_destroy.argtypes = [vp]
+    lib.orc_sharded_set_filter.argtypes = [vp, vp, u64]
+    lib.orc_sharded_insert.argtypes = [vp, ctypes.POINTER(_Records), u64]
+    lib.orc_sharded_update.restype = u64
+    lib.orc_sharded_update.argtypes = [vp]
+    lib.orc_sharded_query.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
+    lib.orc_sharded_count.restype = u64
+    lib.orc_sharded_count.argtypes = [vp]
+    lib.orc_sharded_export.restype = u64
+    lib.orc_sharded_export.argtypes = [vp, vp, vp, vp, vp, vp, u64]
+    lib.orc_sharded_counters.argtypes = [vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -198,6 +211,87 @@ class Oracle:
         a = np.zeros(3, dtype=np.uint64)
         self._lib.orc_counters(self._h, a[0:].ctypes.data, a[1:].ctypes.data, a[2:].ctypes.data)
         return {"skipped": int(a[0]), "coord_overflow": int(a[1]), "inserted": int(a[2])}
+
+
+class ShardedOracle(Oracle):
+    """The same table split by key over `threads` host threads (one std::map
+    per thread; a cell's samples arrive in array order on its own thread, so
+    the results equal the single-threaded oracle's bit for bit).  Supports
+    insert, update, query, set_filter, export, count, counters and keys."""
+
+    def __init__(self, threads: int, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0, max_level=15,
+                 normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
+                 alpha_mode=ALPHA_PAPER, alpha=0.2, t_max=5.0, weighted=0, **_ignored):
+        # a single oracle of the same configuration answers keys()
+        super().__init__(cam=cam, kappa=kappa, e_min=e_min, max_level=max_level,
+                         normal_bins_log2=normal_bins_log2, dir_bins_log2=dir_bins_log2, rough_thr=rough_thr,
+                         alpha_mode=alpha_mode, alpha=alpha, t_max=t_max, weighted=weighted)
+        self.threads = max(1, int(threads))
+        cam_arr = (ctypes.c_float * 3)(*[float(c) for c in cam])
+        self._s = self._lib.orc_sharded_create(self.threads, cam_arr, float(np.float32(kappa)), int(e_min),
+                                               int(max_level), int(normal_bins_log2), int(dir_bins_log2),
+                                               float(np.float32(rough_thr)), int(alpha_mode),
+                                               float(np.float32(alpha)), float(np.float32(t_max)))
+
+    def close(self):
+        if getattr(self, "_s", None):
+            self._lib.orc_sharded_destroy(self._s)
+            self._s = None
+        super().close()
+
+    def set_filter(self, keys):
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        self._lib.orc_sharded_set_filter(self._s, k.ctypes.data if k.size else None, int(k.size))
+
+    def insert(self, rec):
+        if rec.get("weight") is not None and not self.weighted:
+            raise ValueError("weights need a weighted table")
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        self._lib.orc_sharded_insert(self._s, ctypes.byref(p.s), n)
+
+    def update(self) -> int:
+        return int(self._lib.orc_sharded_update(self._s))
+
+    def query(self, rec):
+        n = self._n(rec)
+        p = _Pack(rec, n)
+        out = np.zeros((3, n), dtype=np.float64)
+        found = np.zeros(n, dtype=np.uint8)
+        self._lib.orc_sharded_query(self._s, ctypes.byref(p.s), n, out.ctypes.data, found.ctypes.data)
+        return out, found
+
+    def count(self) -> int:
+        return int(self._lib.orc_sharded_count(self._s))
+
+    def export(self):
+        cap = self.count()
+        keys = np.zeros(cap, dtype=np.uint64)
+        n_new = np.zeros(cap, dtype=np.float64)
+        c_old = np.zeros(cap, dtype=np.float64)
+        L = np.zeros((3, cap), dtype=np.float64)
+        s = np.zeros((3, cap), dtype=np.float64)
+        if cap:
+            got = self._lib.orc_sharded_export(self._s, keys.ctypes.data, n_new.ctypes.data, c_old.ctypes.data,
+                                               L.ctypes.data, s.ctypes.data, cap)
+            assert got == cap
+        if not self.weighted:
+            n_new, c_old = n_new.astype(np.uint64), c_old.astype(np.uint64)
+        return {"keys": keys, "n_new": n_new, "c_old": c_old, "L": L, "s": s}
+
+    def counters(self):
+        a = np.zeros(3, dtype=np.uint64)
+        self._lib.orc_sharded_counters(self._s, a[0:].ctypes.data, a[1:].ctypes.data, a[2:].ctypes.data)
+        return {"skipped": int(a[0]), "coord_overflow": int(a[1]), "inserted": int(a[2])}
+
+    def query_levels(self, rec, up: int):
+        raise NotImplementedError("the sharded oracle answers plain lookups only")
+
+    def reset(self, what: int):
+        raise NotImplementedError("the sharded oracle has no reset")
+
+    def reset_region(self, lo, hi):
+        raise NotImplementedError("the sharded oracle has no reset")
 
 
 # --------------------------------------------------------------------------

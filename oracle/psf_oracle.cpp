@@ -34,7 +34,8 @@
 //     left by the last completed temporal blend.
 //
 // Accumulation and blending are in binary64.  The table is a std::map with no
-// capacity limit.
+// capacity limit.  A key-sharded variant (orc_sharded_*, at the end) runs
+// the same per-cell arithmetic on several host threads, one map per thread.
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (see build.py).
 
@@ -42,6 +43,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <set>
 #include <vector>
 
@@ -290,6 +292,17 @@ void orc_set_filter(void* h, const uint64_t* keys, uint64_t n) {
 // Eq. 5-6 with box basis: per cell, the counter (sum of the MIS weights w of
 // its samples, 1 each without weights) and the sum of w times the sample
 // value, in array order.
+static void accumulate(Oracle* o, uint64_t key, float R, float G, float B, float w) {
+  if (o->filtered && o->filter.count(key) == 0) return;
+  Cell& c = o->cells[key];
+  const double wd = (double)w;
+  c.n_new += wd;
+  c.s[0] += wd * (double)R;
+  c.s[1] += wd * (double)G;
+  c.s[2] += wd * (double)B;
+  o->inserted++;
+}
+
 void orc_insert(void* h, const orc_records* r, uint64_t n) {
   Oracle* o = static_cast<Oracle*>(h);
   const float* const* f = r->f;
@@ -302,14 +315,7 @@ void orc_insert(void* h, const orc_records* r, uint64_t n) {
       continue;
     }
     if (k.overflow) o->coord_overflow++;
-    if (o->filtered && o->filter.count(k.key) == 0) continue;
-    Cell& c = o->cells[k.key];
-    const double wd = (double)w;
-    c.n_new += wd;
-    c.s[0] += wd * (double)R;
-    c.s[1] += wd * (double)G;
-    c.s[2] += wd * (double)B;
-    o->inserted++;
+    accumulate(o, k.key, R, G, B, w);
   }
 }
 
@@ -444,6 +450,178 @@ void orc_counters(void* h, uint64_t* skipped, uint64_t* coord_overflow, uint64_t
   *skipped = o->skipped;
   *coord_overflow = o->coord_overflow;
   *inserted = o->inserted;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// Key-sharded variant on several host threads (the CPU baseline's all-cores
+// line; tests also use it to keep large sampled runs short).  T single-
+// threaded oracles; cell key k belongs to shard owner(k) (a multiplicative
+// hash of the key).  Cells are independent and each shard sees its cells'
+// samples in array order, so every cell gets exactly the arithmetic, in the
+// same order, as in the single oracle: the results are identical.
+struct Sharded {
+  std::vector<Oracle*> shard;
+  std::vector<uint64_t> key;    // per record: key, or ~0 when rejected
+  std::vector<uint8_t> ovf;
+};
+
+static uint32_t owner(uint64_t key, uint32_t t) {
+  return (uint32_t)(((key * 0x9E3779B97F4A7C15ull) >> 32) % t);
+}
+
+template <class F>
+static void parallel(uint32_t t, F&& f) {
+  std::vector<std::thread> th;
+  for (uint32_t i = 1; i < t; ++i) th.emplace_back(f, i);
+  f(0u);
+  for (auto& x : th) x.join();
+}
+
+extern "C" {
+
+void* orc_sharded_create(uint32_t threads, const float* cam, float kappa, int e_min, int max_level,
+                         int normal_bins_log2, int dir_bins_log2, float rough_thr, int alpha_mode, float alpha,
+                         float t_max) {
+  if (threads == 0) threads = 1;
+  Sharded* s = new Sharded();
+  for (uint32_t i = 0; i < threads; ++i)
+    s->shard.push_back(static_cast<Oracle*>(orc_create(cam, kappa, e_min, max_level, normal_bins_log2,
+                                                       dir_bins_log2, rough_thr, alpha_mode, alpha, t_max)));
+  return s;
+}
+
+void orc_sharded_destroy(void* h) {
+  Sharded* s = static_cast<Sharded*>(h);
+  for (Oracle* o : s->shard) delete o;
+  delete s;
+}
+
+void orc_sharded_set_filter(void* h, const uint64_t* keys, uint64_t n) {
+  Sharded* s = static_cast<Sharded*>(h);
+  const uint32_t t = (uint32_t)s->shard.size();
+  for (uint32_t i = 0; i < t; ++i) {
+    Oracle* o = s->shard[i];
+    o->filter.clear();
+    o->filtered = n > 0;
+    for (uint64_t j = 0; j < n; ++j)
+      if (owner(keys[j], t) == i) o->filter.insert(keys[j]);
+  }
+}
+
+// As orc_insert: keys in parallel over record ranges, then every shard takes
+// its own cells' samples in array order.  Skips and overflows are counted
+// on shard 0.
+void orc_sharded_insert(void* h, const orc_records* r, uint64_t n) {
+  Sharded* s = static_cast<Sharded*>(h);
+  const uint32_t t = (uint32_t)s->shard.size();
+  s->key.assign(n, ~0ull);
+  s->ovf.assign(n, 0);
+  std::vector<uint64_t> skipped(t, 0), overflow(t, 0);
+  const float* const* f = r->f;
+  parallel(t, [&](uint32_t i) {
+    const Config& c = s->shard[0]->cfg;
+    const uint64_t lo = n * i / t, hi = n * (i + 1) / t;
+    for (uint64_t j = lo; j < hi; ++j) {
+      float R = f[9][j], G = f[10][j], B = f[11][j];
+      float w = f[14] ? f[14][j] : 1.0f;
+      KeyResult k = key_at(c, r, j);
+      if (!k.valid || !finite3(R, G, B) || !(std::isfinite(w) && w > 0.0f)) {
+        skipped[i]++;
+        continue;
+      }
+      if (k.overflow) overflow[i]++;
+      s->key[j] = k.key;
+    }
+  });
+  parallel(t, [&](uint32_t i) {
+    Oracle* o = s->shard[i];
+    for (uint64_t j = 0; j < n; ++j) {
+      const uint64_t k = s->key[j];
+      if (k == ~0ull || owner(k, t) != i) continue;
+      accumulate(o, k, f[9][j], f[10][j], f[11][j], f[14] ? f[14][j] : 1.0f);
+    }
+  });
+  for (uint32_t i = 0; i < t; ++i) {
+    s->shard[0]->skipped += skipped[i];
+    s->shard[0]->coord_overflow += overflow[i];
+  }
+}
+
+uint64_t orc_sharded_update(void* h) {
+  Sharded* s = static_cast<Sharded*>(h);
+  const uint32_t t = (uint32_t)s->shard.size();
+  std::vector<uint64_t> touched(t, 0);
+  parallel(t, [&](uint32_t i) { touched[i] = orc_update(s->shard[i]); });
+  uint64_t sum = 0;
+  for (uint64_t v : touched) sum += v;
+  return sum;
+}
+
+// As orc_query, over record ranges in parallel (lookups only read).
+void orc_sharded_query(void* h, const orc_records* r, uint64_t n, double* out_rgb, uint8_t* found) {
+  Sharded* s = static_cast<Sharded*>(h);
+  const uint32_t t = (uint32_t)s->shard.size();
+  parallel(t, [&](uint32_t i) {
+    const Config& c = s->shard[0]->cfg;
+    const uint64_t lo = n * i / t, hi = n * (i + 1) / t;
+    for (uint64_t j = lo; j < hi; ++j) {
+      KeyResult k = key_at(c, r, j);
+      double v[3] = {0.0, 0.0, 0.0};
+      uint8_t hit = 0;
+      if (k.valid) {
+        const Oracle* o = s->shard[owner(k.key, t)];
+        auto it = o->cells.find(k.key);
+        if (it != o->cells.end() && it->second.c_old > 0.0) {
+          hit = 1;
+          for (int ch = 0; ch < 3; ++ch) v[ch] = it->second.L[ch];
+        }
+      }
+      out_rgb[j] = v[0];
+      out_rgb[n + j] = v[1];
+      out_rgb[2 * n + j] = v[2];
+      if (found) found[j] = hit;
+    }
+  });
+}
+
+uint64_t orc_sharded_count(void* h) {
+  uint64_t c = 0;
+  for (Oracle* o : static_cast<Sharded*>(h)->shard) c += o->cells.size();
+  return c;
+}
+
+// As orc_export: every shard's cells, merged into ascending key order.
+uint64_t orc_sharded_export(void* h, uint64_t* keys, double* n_new, double* c_old, double* L, double* s_out,
+                            uint64_t cap) {
+  Sharded* s = static_cast<Sharded*>(h);
+  std::map<uint64_t, const Cell*> all;
+  for (Oracle* o : s->shard)
+    for (auto& kv : o->cells) all.emplace(kv.first, &kv.second);
+  uint64_t i = 0;
+  for (auto& kv : all) {
+    if (i >= cap) break;
+    const Cell& c = *kv.second;
+    keys[i] = kv.first;
+    if (n_new) n_new[i] = c.n_new;
+    if (c_old) c_old[i] = c.c_old;
+    for (int ch = 0; ch < 3; ++ch) {
+      if (L) L[ch * cap + i] = c.L[ch];
+      if (s_out) s_out[ch * cap + i] = c.s[ch];
+    }
+    ++i;
+  }
+  return i;
+}
+
+void orc_sharded_counters(void* h, uint64_t* skipped, uint64_t* coord_overflow, uint64_t* inserted) {
+  Sharded* s = static_cast<Sharded*>(h);
+  *skipped = s->shard[0]->skipped;
+  *coord_overflow = s->shard[0]->coord_overflow;
+  uint64_t ins = 0;
+  for (Oracle* o : s->shard) ins += o->inserted;
+  *inserted = ins;
 }
 
 }  // extern "C"

@@ -139,7 +139,8 @@ bool validate(const psf_config* c, std::string* why) {
     return bad("alpha must be in (0, 1]");
   if (c->alpha_mode == PSF_ALPHA_PAPER && !(std::isfinite(c->t_max) && c->t_max >= 1.0f))
     return bad("t_max must be finite and >= 1");
-  if (c->state_dtype < 0 || c->state_dtype > 2) return bad("state_dtype must be F32, F16 or BF16");
+  if (c->state_dtype < 0 || c->state_dtype > 4)
+    return bad("state_dtype must be F32, F16, BF16, F16_EF or BF16_EF");
   if (c->insert_mode < 0 || c->insert_mode > 2) return bad("insert_mode must be AUTO, DIRECT or PARTITIONED");
   if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
   if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS))

@@ -257,12 +257,21 @@ __device__ __forceinline__ float f16_to_f32(uint32_t h) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
 }
 
+// State formats: 0 binary32; 1 binary16 and 2 bfloat16, each re-rounded by
+// every blend; 3 and 4 the same 16-bit values plus each channel's binary32
+// rounding residual (value - stored 16-bit value, exact) kept in the slot's
+// otherwise unused words, so that the blend continues from the unrounded
+// binary32 state and a lookup sees a single rounding.
+__device__ __forceinline__ bool state_is_f16(int32_t dtype) { return dtype == 1 || dtype == 3; }
+__device__ __forceinline__ bool state_has_residual(int32_t dtype) { return dtype >= 3; }
+
+// The approximant a lookup returns.
 __device__ __forceinline__ void load_state(const Slot& s, int32_t dtype, float& r, float& g, float& b) {
   if (dtype == 0) {
     r = __uint_as_float(s.L[0]);
     g = __uint_as_float(s.L[1]);
     b = __uint_as_float(s.L[2]);
-  } else if (dtype == 1) {
+  } else if (state_is_f16(dtype)) {
     r = f16_to_f32(s.L[0] & 0xffffu);
     g = f16_to_f32(s.L[0] >> 16);
     b = f16_to_f32(s.L[1] & 0xffffu);
@@ -273,23 +282,46 @@ __device__ __forceinline__ void load_state(const Slot& s, int32_t dtype, float& 
   }
 }
 
+// The state the blend continues from: the lookup value, plus the carried
+// residual in formats 3 and 4.
+__device__ __forceinline__ void load_blend_state(const Slot& s, int32_t dtype, float& r, float& g, float& b) {
+  load_state(s, dtype, r, g, b);
+  if (state_has_residual(dtype)) {
+    r = r + __uint_as_float(s.L[2]);
+    g = g + __uint_as_float(s.L[3]);
+    b = b + __uint_as_float(s.pad);
+  }
+}
+
+// Encode a blended value: out[0..3] become Slot::L, *pad Slot::pad.
 __device__ __forceinline__ void encode_state(int32_t dtype, float r, float g, float b, uint32_t out[4],
-                                             bool& sat) {
+                                             uint32_t& pad, bool& sat) {
+  pad = 0u;
   if (dtype == 0) {
     out[0] = __float_as_uint(r);
     out[1] = __float_as_uint(g);
     out[2] = __float_as_uint(b);
     out[3] = 0u;
-  } else if (dtype == 1) {
-    out[0] = f32_to_f16_rne(r, sat) | (f32_to_f16_rne(g, sat) << 16);
-    out[1] = f32_to_f16_rne(b, sat);
-    out[2] = 0u;
-    out[3] = 0u;
-  } else {
-    out[0] = f32_to_bf16_rne(r, sat) | (f32_to_bf16_rne(g, sat) << 16);
-    out[1] = f32_to_bf16_rne(b, sat);
-    out[2] = 0u;
-    out[3] = 0u;
+    return;
+  }
+  const bool f16 = state_is_f16(dtype);
+  const uint32_t hr = f16 ? f32_to_f16_rne(r, sat) : f32_to_bf16_rne(r, sat);
+  const uint32_t hg = f16 ? f32_to_f16_rne(g, sat) : f32_to_bf16_rne(g, sat);
+  const uint32_t hb = f16 ? f32_to_f16_rne(b, sat) : f32_to_bf16_rne(b, sat);
+  out[0] = hr | (hg << 16);
+  out[1] = hb;
+  out[2] = 0u;
+  out[3] = 0u;
+  if (state_has_residual(dtype)) {
+    // value - stored value: exact in binary32 (the two are within one
+    // 16-bit ulp of each other), except past F16 saturation, where the
+    // difference itself rounds
+    const float sr = f16 ? f16_to_f32(hr) : bf16_to_f32(hr);
+    const float sg = f16 ? f16_to_f32(hg) : bf16_to_f32(hg);
+    const float sb = f16 ? f16_to_f32(hb) : bf16_to_f32(hb);
+    out[2] = __float_as_uint(r - sr);
+    out[3] = __float_as_uint(g - sg);
+    pad = __float_as_uint(b - sb);
   }
 }
 

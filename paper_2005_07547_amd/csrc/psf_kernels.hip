@@ -186,15 +186,16 @@ __device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParam
   const float alpha = blend_alpha(bp, a.n, c_old, wtd);
   const float inv = 1.0f / counter_value(a.n, wtd);
   float L[3];
-  load_state(*d, bp.dtype, L[0], L[1], L[2]);
+  load_blend_state(*d, bp.dtype, L[0], L[1], L[2]);
   float out[3];
   for (int c = 0; c < 3; ++c) {
     const float m = a.s[c] * inv;
     out[c] = alpha == 1.0f ? m : (1.0f - alpha) * L[c] + alpha * m;
   }
-  uint32_t enc[4];
-  encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
+  uint32_t enc[4], pad;
+  encode_state(bp.dtype, out[0], out[1], out[2], enc, pad, sat);
   d->c_old = counter_add(c_old, a.n, wtd);
+  d->pad = pad;
   *reinterpret_cast<uint4*>(d->L) = make_uint4(enc[0], enc[1], enc[2], enc[3]);
   tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
   return true;

@@ -570,7 +570,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       if (kFused) {
         const float alpha = blend_alpha(bp, c, old[j].c_old, wtd);
         float L[3];
-        load_state(old[j], bp.dtype, L[0], L[1], L[2]);
+        load_blend_state(old[j], bp.dtype, L[0], L[1], L[2]);
         // the new sample mean, rounded once from binary64
         const double cd = wtd ? (double)__uint_as_float(c) : (double)c;
         const float means[3] = {(float)(s_sum0[s] / cd), (float)(s_sum1[s] / cd), (float)(s_sum2[s] / cd)};
@@ -579,12 +579,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           const float m = means[ch];
           out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
         }
-        uint32_t enc[4];
-        encode_state(bp.dtype, out[0], out[1], out[2], enc, sat);
+        uint32_t enc[4], pad;
+        encode_state(bp.dtype, out[0], out[1], out[2], enc, pad, sat);
         Slot nw;
         nw.key = k;
         nw.c_old = counter_add(old[j].c_old, c, wtd);
-        nw.pad = 0;
+        nw.pad = pad;
         nw.L[0] = enc[0];
         nw.L[1] = enc[1];
         nw.L[2] = enc[2];

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpsf.so")
 PSF_OK, PSF_INVALID_ARGUMENT, PSF_OUT_OF_MEMORY, PSF_BUFFER_TOO_SMALL, PSF_HIP_ERROR, \
     PSF_NOT_SUPPORTED = range(6)
 PSF_ALPHA_PAPER, PSF_ALPHA_CONST, PSF_ALPHA_LINEAR = 0, 1, 2
-PSF_STATE_F32, PSF_STATE_F16, PSF_STATE_BF16 = 0, 1, 2
+PSF_STATE_F32, PSF_STATE_F16, PSF_STATE_BF16, PSF_STATE_F16_EF, PSF_STATE_BF16_EF = 0, 1, 2, 3, 4
 PSF_RESET_COUNTERS, PSF_RESET_CLEAR, PSF_RESET_STATS = 1, 2, 4
 PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
 PSF_FLAG_PROBE_STATS = 1

@@ -90,7 +90,8 @@ class Server:
 
     def _retire(self, s: SessionRequest, now: float):
         s.finished_at = now
-        s.out = s.found = None
+        if not self.keep_tables:
+            s.out = s.found = None
         self._retired.append(s)
 
     def _flush(self):

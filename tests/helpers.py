@@ -64,6 +64,18 @@ def gpu_available():
         return False
 
 
+# Relative error bounds of the stored approximant against the binary64
+# oracle, per state format (psf_config.state_dtype), in the format's normal
+# range.  Blend arithmetic is binary32 (FP32 state: 1e-5, the target's
+# tolerance).  A 16-bit format re-rounded by every blend carries, per Sec.
+# 2.4's recursion E_k = (1 - a_k) E_(k-1) + d_k with |d_k| <= u |L_k| and
+# a_k >= 1/T_max, at most u T_max (T_max = 5 in every workload here); with
+# the residual carried (error feedback) a lookup sees one rounding: u.
+U_F16, U_BF16, T_MAX_WORKLOADS = 2.0 ** -11, 2.0 ** -8, 5.0
+STATE_BOUND = {0: 1e-5, 1: U_F16 * T_MAX_WORKLOADS, 2: U_BF16 * T_MAX_WORKLOADS,
+               3: U_F16 + 1e-5, 4: U_BF16 + 1e-5}
+
+
 def rel_err(got, want):
     got = np.asarray(got, dtype=np.float64)
     want = np.asarray(want, dtype=np.float64)

@@ -185,3 +185,62 @@ def test_wide_partition_session_runs_alone_with_the_same_result(env):
     for a, m in zip(alone, mixed):
         ea, em = a.export(), m.export()
         assert np.array_equal(ea["keys"], em["keys"]) and np.array_equal(ea["c_old"], em["c_old"])
+
+
+@pytest.mark.timeout(600)
+def test_full_size_batched_sessions_sampled_cells(env):
+    """The batched workload at its stated size: 16 uneven sessions (256x256
+    to 1920x1080, 1-4 spp, 3-5 vertices, 2^18-2^23-slot tables, about 115M
+    records per iteration) through one batched call per iteration, 2
+    iterations.  A sample of each session's cells is tracked by the binary64
+    oracle (key-sharded over the host threads): keys and counts bit-exact,
+    FP32 state within 1e-5, and every record that falls in a sampled cell
+    gets the oracle's lookup from the fused answer pass."""
+    import os
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    wls = W.batched_sessions(16)
+    scs = [W.make_scene(wl) for wl in wls]
+    ns = [W.records_per_iteration(wl) for wl in wls]
+    assert sum(ns) > 100_000_000
+    tables = [psf.Table(**dict(wl["table"], max_batch=n)) for wl, n in zip(wls, ns)]
+    threads = min(16, os.cpu_count() or 1)
+    orcs = [oracle.ShardedOracle(threads, **wl["table"]) for wl in wls]
+    batch = psf.Batch(16)
+    rng = np.random.default_rng(31)
+    samples = []
+    for it in range(2):
+        recs = [sc.generate(wl["gen"], it) for wl, sc in zip(wls, scs)]
+        if it == 0:
+            for o, r in zip(orcs, recs):
+                k, _ = o.keys(r)
+                s = np.unique(rng.choice(k[k != np.uint64(2 ** 64 - 1)], size=3000))
+                o.set_filter(s)
+                samples.append(s)
+        dev = [to_device(r) for r in recs]
+        res = batch.iterate(tables, dev)
+        for o, r in zip(orcs, recs):
+            o.insert(r)
+            o.update()
+        torch.cuda.synchronize()
+        del dev
+        print(f"iteration {it + 1}: {sum(ns)} records in 16 sessions", flush=True)
+    for i in range(16):
+        o = orcs[i].export()
+        g = tables[i].export()
+        idx = np.searchsorted(g["keys"], o["keys"])
+        assert np.all(g["keys"][idx] == o["keys"]), i
+        assert np.array_equal(g["c_old"][idx].astype(np.uint64), o["c_old"]), i
+        assert np.array_equal(g["n_new"][idx].astype(np.uint64), o["n_new"]), i
+        assert rel_err(g["L"][:, idx], o["L"]).max() <= RTOL_F32, i
+        assert tables[i].stats()["dropped"] == 0, i
+        # the fused answers of the last iteration at the records of sampled cells
+        k, _ = orcs[i].keys(recs[i])
+        pick = np.nonzero(np.isin(k, samples[i]))[0]
+        assert pick.size > 0
+        sub = {f: (None if v is None else v[pick]) for f, v in recs[i].items()}
+        w_out, w_found = orcs[i].query(sub)
+        out, found = res[i]
+        assert np.array_equal(found.cpu().numpy()[pick], w_found), i
+        assert rel_err(out.cpu().numpy()[:, pick], w_out).max() <= RTOL_F32, i

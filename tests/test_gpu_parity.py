@@ -9,7 +9,7 @@ workload (sampled cells).
 import numpy as np
 import pytest
 
-from tests.helpers import (compare_cells, concat, golden_rows, records, rel_err, take, to_device)
+from tests.helpers import (STATE_BOUND, compare_cells, concat, golden_rows, records, rel_err, take, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -373,7 +373,7 @@ def test_invalid_arguments(psf, torch_cuda):
     assert lib.psf_insert_samples(t.handle, None, 0, None) == psf.PSF_OK
     assert lib.psf_reset(t.handle, 64, None) == psf.PSF_INVALID_ARGUMENT
     for kw in (dict(alpha_mode=1, alpha=0.0), dict(t_max=0.5), dict(kappa=-1.0), dict(max_level=16),
-               dict(dir_bins_log2=4), dict(state_dtype=3), dict(part_log2=5), dict(max_probe=0)):
+               dict(dir_bins_log2=4), dict(state_dtype=5), dict(part_log2=5), dict(max_probe=0)):
         c = psf.make_config(log2_slots=10, **kw)
         assert lib.psf_table_bytes(ctypes.byref(c)) == 0, kw
 
@@ -434,6 +434,8 @@ def _fused_cases():
         ("transposed", dict(flags=4), same),
         ("f16", dict(state_dtype=1), same),
         ("bf16", dict(state_dtype=2), same),
+        ("f16-residual", dict(state_dtype=3), same),
+        ("bf16-residual", dict(state_dtype=4), same),
     ]
 
 
@@ -463,7 +465,7 @@ def test_fused_query_equals_lookup(psf, torch_cuda, case):
     if st["dropped"] == 0:
         w_out, w_found = orc.query(rec)
         assert np.array_equal(found.cpu().numpy(), w_found), label
-        tol = RTOL_F32 if cfg.get("state_dtype", 0) == 0 else 1e-2
+        tol = STATE_BOUND[cfg.get("state_dtype", 0)]
         assert rel_err(out.cpu().numpy(), w_out).max() <= tol, label
     else:
         assert label in ("overflow", "max_probe=1", "dense", "dense-transposed"), (label, st["dropped"])

@@ -3,7 +3,7 @@ checked against the binary64 oracle."""
 import numpy as np
 import pytest
 
-from tests.helpers import compare_cells, records, rel_err, to_device
+from tests.helpers import STATE_BOUND, T_MAX_WORKLOADS, compare_cells, records, rel_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_bf16_round_to_nearest_even(env):
     assert np.isfinite(L[0]) and st["saturated"] == 0
 
 
-@pytest.mark.parametrize("dtype_name", ["F16", "BF16"])
+@pytest.mark.parametrize("dtype_name", ["F16", "BF16", "F16_EF", "BF16_EF"])
 def test_tiny_workload_reduced_precision_keys_and_counts_exact(env, dtype_name):
     import oracle
     from synth import workloads as W
@@ -64,70 +64,124 @@ def test_tiny_workload_reduced_precision_keys_and_counts_exact(env, dtype_name):
     wl = W.tiny(alpha_mode=W.ALPHA_PAPER)
     sc = W.make_scene(wl)
     orc = oracle.Oracle(**wl["table"])
-    t = psf.Table(**dict(wl["table"], state_dtype=getattr(psf, f"PSF_STATE_{dtype_name}")))
+    code = getattr(psf, f"PSF_STATE_{dtype_name}")
+    t = psf.Table(**dict(wl["table"], state_dtype=code))
     for it in range(wl["iterations"]):
         rec = dict(sc.generate(wl["gen"], it))
         rec["rough"] = None
         t.iterate(to_device(rec))
         orc.insert(rec)
         orc.update()
-    tol = {"F16": 2.5e-3, "BF16": 2.0e-2}[dtype_name]
-    worst = compare_cells(t.export(), orc.export(), tol, dtype_name)
+    worst = compare_cells(t.export(), orc.export(), STATE_BOUND[code], dtype_name)
     print(f"tiny {dtype_name}: worst relative error {worst:.3e}")
 
 
-# Error model of the stored approximant (Sec. 2.4 blend, FP32 arithmetic,
-# round-to-nearest-even store of a 16-bit format with unit roundoff u):
-# E_k = (1 - a_k) E_{k-1} + d_k with |d_k| <= u |L_k|, so with a_k >= 1/T_max
-# the steady-state error is at most u * T_max * max|L| over the window.
-U_F16, U_BF16, T_MAX = 2.0 ** -11, 2.0 ** -8, 5.0
+def test_residual_formats_blend_from_the_unrounded_state(env):
+    """A cell blended with constant alpha from 1/3 toward 1/3 + k eps: the
+    residual-carrying formats continue from the FP32 value (so the stored
+    value is the FP32 result rounded once) while the plain ones re-round."""
+    torch, psf = env
+    vals = [1.0 / 3.0 + 1e-4 * k for k in range(6)]
+    got = {}
+    for name in ("F32", "F16", "F16_EF", "BF16", "BF16_EF"):
+        t = psf.Table(log2_slots=8, state_dtype=getattr(psf, f"PSF_STATE_{name}"), alpha_mode=psf.PSF_ALPHA_CONST,
+                      alpha=0.3)
+        for v in vals:
+            t.iterate(to_device(records(1, px=0.5, py=0.5, pz=0.5, r=v, g=2 * v, b=-v)))
+        got[name] = t.export()["L"][:, 0].astype(np.float32)
+        t.close()
+    f32 = got["F32"]
+    assert np.array_equal(got["F16_EF"], f32.astype(np.float16).astype(np.float32))
+    bf = (f32.view(np.uint32).astype(np.uint64) + 0x7FFF + ((f32.view(np.uint32) >> 16) & 1)) >> 16
+    assert np.array_equal(got["BF16_EF"], (bf.astype(np.uint32) << 16).view(np.float32))
 
 
+def _prefetch(gen, n_frames):
+    """Frames generated one ahead on a host thread (the generator releases
+    the GIL), so generation overlaps the GPU and oracle work."""
+    from concurrent.futures import ThreadPoolExecutor
+    ex = ThreadPoolExecutor(max_workers=1)
+    fut = ex.submit(gen, 0)
+    for it in range(n_frames):
+        rec = fut.result()
+        if it + 1 < n_frames:
+            fut = ex.submit(gen, it + 1)
+        yield it, rec
+    ex.shutdown()
+
+
+@pytest.mark.timeout(600)
 def test_precision_workload_sampled_cells(env):
     """1920x1080, 5 vertices/path (10,368,000 records/iteration), 2^24
-    slots, lognormal(0, 2) radiance: FP32, FP16 and BF16 tables fed the same
-    frames; a sample of cells tracked by the binary64 oracle."""
+    slots, lognormal(0, 2) radiance, all 64 iterations: FP32 and the four
+    16-bit formats fed the same frames; a sample of cells tracked by the
+    binary64 oracle (key-sharded over the host threads).  Keys and counts
+    bit-exact; the approximant within each format's bound in the normal
+    range; outside it, an absolute bound (subnormal F16) or saturation."""
+    import os
     import oracle
     from synth import workloads as W
     torch, psf = env
     wl = W.precision()
-    iters = 16
+    iters = wl["iterations"]
+    assert iters == 64
     sc = W.make_scene(wl)
     n = W.records_per_iteration(wl)
-    tabs = {name: psf.Table(**dict(wl["table"], state_dtype=getattr(psf, f"PSF_STATE_{name}"),
-                                   max_batch=n))
-            for name in ("F32", "F16", "BF16")}
-    orc = oracle.Oracle(**wl["table"])
-    first = sc.generate(wl["gen"], 0)
-    k0, _ = orc.keys(first)
+    names = ("F32", "F16", "BF16", "F16_EF", "BF16_EF")
+    tabs = {name: psf.Table(**dict(wl["table"], state_dtype=getattr(psf, f"PSF_STATE_{name}"), max_batch=n))
+            for name in names}
+    orc = oracle.ShardedOracle(min(16, os.cpu_count() or 1), **wl["table"])
     rng = np.random.default_rng(3)
-    sample = np.unique(rng.choice(k0[k0 != np.uint64(2 ** 64 - 1)], size=4000))
-    orc.set_filter(sample)
-    for it in range(iters):
-        rec = first if it == 0 else sc.generate(wl["gen"], it)
+    for it, rec in _prefetch(lambda i: sc.generate(wl["gen"], i), iters):
+        if it == 0:
+            k0, _ = orc.keys(rec)
+            sample = np.unique(rng.choice(k0[k0 != np.uint64(2 ** 64 - 1)], size=8000))
+            orc.set_filter(sample)
         d = to_device(rec)
         for t in tabs.values():
             t.iterate(d)
         orc.insert(rec)
         orc.update()
         del d
+        if it % 16 == 15:
+            print(f"iteration {it + 1}/{iters}", flush=True)
     torch.cuda.synchronize()
     o = orc.export()
+    ref = o["L"]
     report = {}
     for name, t in tabs.items():
+        code = getattr(psf, f"PSF_STATE_{name}")
         g = t.export()
         idx = np.searchsorted(g["keys"], o["keys"])
-        assert np.all(g["keys"][idx] == o["keys"])
+        assert np.all(g["keys"][idx] == o["keys"]), name
         sub = {k: (v[:, idx] if v.ndim == 2 else v[idx]) for k, v in g.items()}
-        assert np.array_equal(sub["c_old"].astype(np.uint64), o["c_old"])
-        ref = o["L"]
-        ok = (np.abs(ref) <= 65504.0) & (np.abs(ref) >= 2.0 ** -14) if name == "F16" else np.ones_like(ref, bool)
-        e = rel_err(sub["L"], ref)[ok]
-        report[name] = (float(e.max()), float(np.percentile(e, 99)), int((~ok).sum()))
-        assert t.stats()["dropped"] == 0
-    print("precision workload relative error (max, p99, excluded):", report)
-    assert report["F32"][0] <= 1e-5
-    assert report["F16"][1] <= 2e-3
-    assert report["F16"][0] <= U_F16 * T_MAX * 2
-    assert report["BF16"][1] <= U_BF16 * T_MAX
-    assert report["BF16"][0] <= U_BF16 * T_MAX * 2
+        assert np.array_equal(sub["c_old"].astype(np.uint64), o["c_old"]), name
+        st = t.stats()
+        assert st["dropped"] == 0, name
+        got = sub["L"].astype(np.float64)
+        if code in (1, 3):
+            small = np.abs(ref) < 2.0 ** -14
+            big = np.abs(ref) > 65504.0
+            ok = ~small & ~big
+            # subnormal F16: spacing 2^-24, so half of it per rounding
+            steps = T_MAX_WORKLOADS if code == 1 else 1.0
+            assert np.all(np.abs(got - ref)[small] <= steps * 2.0 ** -25 + 1e-5 * np.abs(ref[small])), name
+            # past the F16 range the stored value saturates (and is counted)
+            assert np.all(np.abs(got[big]) == 65504.0), name
+            assert (st["saturated"] > 0) or not big.any(), name
+        else:
+            ok = np.ones_like(ref, dtype=bool)
+        e = rel_err(got, ref)[ok]
+        report[name] = {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "excluded": int((~ok).sum()),
+                        "saturated": int(st["saturated"])}
+    print(f"{len(o['keys'])} sampled cells, 64 iterations; relative error vs binary64:", report)
+    assert report["F32"]["max"] <= 1e-5
+    # the target for the FP16 approximant: 2e-3 relative to FP64
+    assert report["F16_EF"]["max"] <= 2e-3
+    assert report["F16_EF"]["max"] <= STATE_BOUND[3]
+    assert report["BF16_EF"]["max"] <= STATE_BOUND[4]
+    # the plain format, re-rounded by every blend, meets it too (measured
+    # max 1.65e-3, p99 9.7e-4), well inside its own bound u T_max
+    assert report["F16"]["max"] <= 2e-3
+    assert report["F16"]["max"] <= STATE_BOUND[1]
+    assert report["BF16"]["max"] <= STATE_BOUND[2]

@@ -27,17 +27,25 @@ def _requests(serving, n=6, scale_classes=(0, 1, 1, 2, 0, 1), iters=(4, 6, 3, 5,
         wl = W.plain()
         gen = dict(wl["gen"], width=w, height=h, seed=900 + i)
         sc = Scene(Scene.RANDOM, seed=900 + i, glossy_frac=-1.0 if i % 2 else 0.5)
-        frames = [to_device(sc.generate(gen, f)) for f in range(2)]
+        host = [sc.generate(gen, f) for f in range(2)]
+        frames = [to_device(h) for h in host]
         # cells sized for this resolution; four slots per record keeps every
         # partition far from full over the session
         cfg = dict(wl["table"], log2_slots=max(16, int(np.ceil(np.log2(w * h * 4))) + 2),
                    kappa=W.kappa_for(60.0, h, 8.0 * np.sqrt(2.0), -5))
-        reqs.append(serving.SessionRequest(sid=i, arrival=arrivals[i], iterations=iters[i],
-                                           table_cfg=cfg, frames=frames, records=w * h * 4))
+        req = serving.SessionRequest(sid=i, arrival=arrivals[i], iterations=iters[i],
+                                     table_cfg=cfg, frames=frames, records=w * h * 4)
+        req.host_frames = host  # the same frames on the host, for the oracle
+        reqs.append(req)
     return reqs
 
 
 def test_results_same_alone_and_in_the_mix(env):
+    """Every served session against the binary64 oracle fed the same frames
+    (keys and counts bit-exact, FP32 state within 1e-5, last answers), and
+    against the same session run alone."""
+    import oracle
+    from tests.helpers import compare_cells
     torch, psf, serving = env
     reqs = _requests(serving)
     srv = serving.Server(budget_bytes=64 << 30, max_active=16, keep_tables=True)
@@ -56,6 +64,15 @@ def test_results_same_alone_and_in_the_mix(env):
         assert r.table.stats()["updates"] == r.iterations
         assert r.table.stats()["dropped"] == 0
         assert len(r.latencies_ms) == r.iterations
+        orc = oracle.Oracle(**r.table_cfg)
+        for it in range(r.iterations):
+            orc.insert(r.host_frames[it % len(r.host_frames)])
+            orc.update()
+        compare_cells(em, orc.export(), RTOL_F32, f"served session {r.sid}")
+        # the served answers of the session's last iteration
+        w_out, w_found = orc.query(r.host_frames[(r.iterations - 1) % len(r.host_frames)])
+        assert np.array_equal(r.found.cpu().numpy(), w_found), r.sid
+        assert rel_err(r.out.cpu().numpy(), w_out).max() <= RTOL_F32, r.sid
 
 
 def test_budget_forces_queueing(env):
