@@ -333,6 +333,19 @@ psf_status psf_get_stats(psf_table* t, psf_stats* out, psf_stream stream);
 psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
                             float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
 
+/* Allocation-free variant of psf_export_cells, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and errors, but the device
+ * staging of the compacted cells lives in a fixed array the library holds
+ * on each GPU for the life of the process (28 MiB + 256 B) instead of a
+ * per-call allocation.  At most 1048576 occupied cells: a table with more
+ * returns PSF_NOT_SUPPORTED (after setting *count), before anything is
+ * compacted.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (from several threads or streams) race; the caller
+ * serialises them.  Synchronises stream. */
+psf_status psf_export_cells_noalloc(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
+                                    float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
+
 /* Batched form: one iteration (insert, temporal update, query) of k
  * independent sessions, each with its own table, in three launches that
  * cover every session (binning, merge + blend, lookup).  Each session's

@@ -3,6 +3,7 @@
 // ABI; every entry point returns a psf_status.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -665,6 +666,82 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
+}
+
+// ------------------------------------------------------------------ allocation-free export
+// Device scratch of psf_export_cells_noalloc: two counters (occupied cells,
+// compaction cursor) in the first 256 bytes, then the compacted cells of at
+// most kNoAllocCells entries (keys, n_new, c_old, rgb).  One copy per GPU,
+// held until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address hipGetSymbolAddress returned for the current device.
+constexpr uint64_t kNoAllocCells = 1ull << 20;
+constexpr size_t kNoAllocBytes = 256 + kNoAllocCells * (8 + 4 + 4 + 12);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// The current device's copy of the scratch array (looked up once per device).
+psf_status scratch_ptr(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(PSF_NOT_SUPPORTED, "allocation-free export: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return PSF_OK;
+}
+}  // namespace
+
+PSF_API psf_status psf_export_cells_noalloc(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
+                                            float* state_rgb, uint64_t cap, uint64_t* count,
+                                            psf_stream stream) {
+  if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  char* d = nullptr;
+  psf_status st = scratch_ptr(&d);
+  if (st != PSF_OK) return st;
+  auto* occ_d = reinterpret_cast<unsigned long long*>(d);
+  auto* cur = occ_d + 1;
+  // counters cleared by a fill kernel (no memset node)
+  hipError_t e = psf::launch_zero(d, 16, s);
+  if (e == hipSuccess) e = psf::launch_count_occupied(t->tv, nslots(t), occ_d, s);
+  unsigned long long occ = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&occ, occ_d, sizeof occ, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "count occupied");
+  *count = occ;
+  if (occ > kNoAllocCells)
+    return fail(PSF_NOT_SUPPORTED, "allocation-free export handles at most 1048576 occupied cells; the table has " +
+                                       std::to_string(occ) + " (use psf_export_cells)");
+  if (occ > cap) return fail(PSF_BUFFER_TOO_SMALL, "more occupied cells than cap");
+  if (occ == 0) return PSF_OK;
+  // the arrays are packed for this call's count, as psf_export_cells packs them
+  auto* dk = reinterpret_cast<unsigned long long*>(d + 256);
+  auto* dn = reinterpret_cast<uint32_t*>(d + 256 + occ * 8);
+  auto* dc = dn + occ;
+  auto* drgb = reinterpret_cast<float*>(dc + occ);
+  e = psf::launch_compact(t->tv, nslots(t), t->cfg.state_dtype, cur, occ, dk, dn, dc, drgb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(keys, dk, occ * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && n_new) e = hipMemcpyAsync(n_new, dn, occ * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && c_old) e = hipMemcpyAsync(c_old, dc, occ * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && state_rgb) {
+    for (int ch = 0; ch < 3 && e == hipSuccess; ++ch)
+      e = hipMemcpyAsync(state_rgb + ch * cap, drgb + ch * occ, occ * 4, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
 }
 

@@ -105,6 +105,7 @@ EXPORTS = [
     ("psf_compute_keys", ctypes.c_int, [_vp, _P(psf_records), _u64, _vp, _vp]),
     ("psf_get_stats", ctypes.c_int, [_vp, _P(psf_stats), _vp]),
     ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
+    ("psf_export_cells_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_batch_create", ctypes.c_int, [_u32, _P(_vp)]),
     ("psf_batch_destroy", ctypes.c_int, [_vp]),
     ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
@@ -333,9 +334,11 @@ class Table:
         return {self._lib.psf_kernel_name(k).decode(): (int(launches[k]), float(ms[k]))
                 for k in range(PSF_K_COUNT) if launches[k]}
 
-    def export(self):
+    def export(self, noalloc: bool = False):
         """Occupied cells as numpy arrays: keys (uint64), n_new, c_old (uint32
-        counts; float32 weight sums for a weighted table), L (3 x C)."""
+        counts; float32 weight sums for a weighted table), L (3 x C).
+        noalloc: through psf_export_cells_noalloc (the library's fixed device
+        array instead of a per-call allocation)."""
         import numpy as np
         st = self.stats()
         cap = max(1, int(st["occupied"]))
@@ -344,9 +347,9 @@ class Table:
         c_old = np.zeros(cap, dtype=np.uint32)
         rgb = np.zeros((3, cap), dtype=np.float32)
         count = ctypes.c_uint64()
-        _check(self._lib.psf_export_cells(self.handle, keys.ctypes.data, n_new.ctypes.data,
-                                          c_old.ctypes.data, rgb.ctypes.data, cap,
-                                          ctypes.byref(count), current_stream()))
+        fn = self._lib.psf_export_cells_noalloc if noalloc else self._lib.psf_export_cells
+        _check(fn(self.handle, keys.ctypes.data, n_new.ctypes.data, c_old.ctypes.data, rgb.ctypes.data, cap,
+                  ctypes.byref(count), current_stream()))
         c = int(count.value)
         order = np.argsort(keys[:c], kind="stable")
         if self.cfg.weighted:
