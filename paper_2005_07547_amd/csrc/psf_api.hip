@@ -153,7 +153,7 @@ bool validate(const psf_config* c, std::string* why) {
 }
 
 struct Layout {
-  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_rgb = 0, stage_w = 0, runs = 0,
+  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_v = 0, runs = 0,
          runs_t = 0, perm = 0, total = 0;
   uint32_t part_log2 = 0;
   bool part = false;
@@ -190,12 +190,8 @@ Layout layout_of(const psf_config& c) {
     L.cap = (uint64_t)L.tiles * tile;
     L.stage_key = off;
     off = align_up(off + L.cap * 8, 256);
-    L.stage_rgb = off;
-    off = align_up(off + L.cap * 12, 256);
-    if (c.weighted) {
-      L.stage_w = off;
-      off = align_up(off + L.cap * 4, 256);
-    }
+    L.stage_v = off;
+    off = align_up(off + L.cap * 16, 256);
     L.runs = off;
     off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
     L.runs_t = off;  // rows padded to a multiple of 4 tiles (16-byte loads)
@@ -265,7 +261,7 @@ psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream
       const psf::RecPtrs sub = offset_rec(rp, off);
       psf::PartView pv = t->pv;
       pv.perm = nullptr;
-      if (!sub.weight) pv.stage_w = nullptr;
+      pv.weights = sub.weight != nullptr;
       const uint32_t nt = (uint32_t)((m + pv.tile - 1) / pv.tile);
       if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
       e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(sub, m, t->kp, t->tv, pv, s); });
@@ -363,8 +359,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if (cfg->alpha_mode != PSF_ALPHA_PAPER) t->bp.inv_t_max = 0.0f;
   if (L.part) {
     t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
-    t->pv.stage_rgb = reinterpret_cast<float*>(b + L.stage_rgb);
-    t->pv.stage_w = cfg->weighted ? reinterpret_cast<float*>(b + L.stage_w) : nullptr;
+    t->pv.stage_v = reinterpret_cast<float4*>(b + L.stage_v);
+    t->pv.weights = 0;
     t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
     t->pv.runs_t = reinterpret_cast<uint32_t*>(b + L.runs_t);
     t->pv.perm = reinterpret_cast<uint16_t*>(b + L.perm);
@@ -460,7 +456,7 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
     const bool fq = nq == n && same_vertices(rec, q);
     psf::PartView pv = t->pv;
     if (!fq) pv.perm = nullptr;
-    if (!rp.weight) pv.stage_w = nullptr;
+    pv.weights = rp.weight != nullptr;
     const uint32_t nt = (uint32_t)((n + pv.tile - 1) / pv.tile);
     if (!transpose_runs(t, nt)) pv.runs_t = nullptr;
     hipError_t e = timed(t, PSF_K_BIN, s, [&] { return psf::launch_bin(rp, n, t->kp, t->tv, pv, s); });
@@ -870,7 +866,7 @@ PSF_API psf_status psf_iterate_batch(psf_batch* b, const psf_session* sessions, 
     d.found = ss.d_out_found;
     d.fused_query = (ss.nq == ss.n && same_vertices(&ss.rec, &ss.q)) ? 1 : 0;
     if (!d.fused_query) d.pv.perm = nullptr;
-    if (!d.rec.weight) d.pv.stage_w = nullptr;
+    d.pv.weights = d.rec.weight != nullptr;
     d.tile_begin = tiles;
     d.ntiles = (uint32_t)((ss.n + t->pv.tile - 1) / t->pv.tile);
     d.part_begin = parts;

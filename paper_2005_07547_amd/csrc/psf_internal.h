@@ -19,12 +19,15 @@ struct QryPtrs {
 
 // Partitioned-insert working buffers of one table.
 struct PartView {
-  unsigned long long* stage_key;  // staged sample keys, grouped per tile by partition
-  float* stage_rgb;               // staged sample values (r, g, b triples), same order
-  float* stage_w;                 // staged weights, same order (null: this launch's
-                                  // records carry none, every weight 1); the merge
-                                  // pass ignores a sample whose weight is not
-                                  // finite and > 0
+  unsigned long long* stage_key;  // staged entry keys, grouped per tile by partition
+  float4* stage_v;                // staged entry values, same order: {r, g, b} sums
+                                  // (w (r, g, b) with weights) and n, the records the
+                                  // entry carries (with weights: the record's weight),
+                                  // as a float; n = 0 marks an entry staged for lookup
+                                  // only (a rejected sample).  The fused query writes
+                                  // each entry's answer {r, g, b, 0} over it.
+  uint32_t weights;               // this launch's records carry weights (n is then a
+                                  // weight, one record per entry)
   uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile
   uint32_t* runs_t;               // the same, transposed: [partition + 1][max_tiles]
                                   // (null: not transposed for this launch)

@@ -6,17 +6,20 @@
 // key is the top bits of its hash, its probe sequence stays inside the
 // partition).  Insertion then runs in two passes:
 //
-//   bin   -- one block per tile of records computes the keys, counts records
-//            per partition in LDS, sorts the tile by partition in LDS and
-//            writes it out coalesced (keys, then rgb triples) to a staging
-//            area, plus the tile's exclusive per-partition offsets (and,
-//            for the fused query, each record's position in the tile);
+//   bin   -- one block per tile of records computes the keys, merges
+//            records of one cell in neighbouring lanes into one entry,
+//            counts entries per partition in LDS, sorts the tile by
+//            partition in LDS and writes it out coalesced (keys, then
+//            16-byte values {r, g, b, n}) to a staging area, plus the tile's
+//            exclusive per-partition offsets (and, for the fused query, each
+//            record's entry position in the tile);
 //   (transpose -- for large launches, the offset table turned so that a
 //            partition's offsets are one row);
 //   merge -- one block per partition loads the partition's keys into LDS,
 //            gathers that partition's entries from every tile, finds or
-//            claims each key's slot and accumulates count (u32) and sums
-//            (binary64) with LDS atomics, then writes the partition back:
+//            claims each key's slot and accumulates count (u32, or binary32
+//            weight sums) and sums (binary64) with LDS atomics, then writes
+//            the partition back:
 //            either adding into the global accumulators (plain insert) or,
 //            when the whole frame is in this launch, applying the temporal
 //            blend (Eq. 10-11) directly so the accumulators never touch HBM;
@@ -38,6 +41,12 @@ constexpr int kMergeThreads = 512;
 constexpr uint32_t kMaxPartLog2 = 12;
 
 bool bin_per_ok(uint32_t per) { return per == 8 || per == 12 || per == 16; }
+
+// LDS staging bytes per record of a binning tile: 16 (every tile's values
+// in one float4 pass) where two blocks per CU still fit, else 12 (a tile
+// with more than 3/4 of its records as entries stages its values in two
+// halves).
+__host__ __device__ constexpr size_t bin_lds_per_record(uint32_t per) { return per <= 8 ? 16 : 12; }
 uint32_t bin_tile(uint32_t per) { return kBinThreads * per; }
 
 // Exclusive prefix sum of cnt[0..m) in LDS, in place; returns the total.
@@ -83,16 +92,45 @@ __device__ uint32_t block_exclusive_scan(uint32_t* cnt, uint32_t m, uint32_t* s_
 
 // ------------------------------------------------------------------ bin
 // Dynamic LDS holds first the partition histogram (P + 1 words), then, once
-// every record knows its place, the tile's staging buffer (tile * 12 bytes:
-// keys, then rgb triples), so that both global writes of the partition-
-// sorted tile are coalesced.
+// every entry knows its place, the tile's staging buffers: keys, then the
+// entries' values {r, g, b, n} (as float4 when they fit, else in two
+// halves), so that every global write of the partition-sorted tile is
+// coalesced.
+//
+// Pre-merge: unless the records carry weights, the records of one wave that
+// fall in the same cell as the lane before them (neighbouring pixels of a
+// scanline usually share a cell at the first bounce) leave a single staged
+// entry: the first lane of each such run carries the run's record count and
+// value sums (a segmented sum over lanes, in a fixed order), and the other
+// records of the run only point at it for the fused query.
+//
 // kX: what the records carry beyond the common fields, kXFootprint (their
-// level rule) and kXWeight (MIS weights, staged beside the values, which
-// stay unweighted; a weight is read only by the staging pass, which also
-// counts the samples it rejects, and the merge pass applies it); separate
-// instantiations keep the extra loads and their registers out of the
-// common case.
+// level rule) and kXWeight (MIS weights: every sample is its own entry with
+// value w (r, g, b) and n = w; a weight is read only after the sort, which
+// also counts the samples it rejects); separate instantiations keep the
+// extra loads and their registers out of the common case.
 constexpr uint32_t kXFootprint = 1, kXWeight = 2;
+
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, uint32_t d) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Records carried by the entry of a run head in lane `lane` (1 + the
+// continuation lanes that follow it); cont has bit l set where lane l
+// continues lane l - 1's run.
+__device__ __forceinline__ uint32_t run_records(unsigned long long cont, uint32_t lane) {
+  const unsigned long long after = lane == 63 ? 0ull : cont >> (lane + 1);
+  return 1u + (uint32_t)__builtin_ctzll(~after);
+}
+
+// Lane of the head of `lane`'s run (the last lane at or before it that does
+// not continue its predecessor).
+__device__ __forceinline__ uint32_t run_head(unsigned long long cont, uint32_t lane) {
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  return 63u - (uint32_t)__builtin_clzll(~cont & upto);
+}
 
 template <uint32_t kPer, uint32_t kX>
 __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
@@ -100,23 +138,29 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   constexpr bool kFp = (kX & kXFootprint) != 0, kW = (kX & kXWeight) != 0;
   extern __shared__ uint32_t s_dyn_bin[];
   __shared__ uint32_t s_wave[kBinThreads / 64 + 1];
+  __shared__ unsigned long long s_cont[kBinThreads / 64][kPer];  // per wave and record row: run continuations
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   uint32_t* s_hist = s_dyn_bin;
   unsigned long long* s_k = reinterpret_cast<unsigned long long*>(s_dyn_bin);
-  float* s_f = reinterpret_cast<float*>(s_dyn_bin);
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
+  const bool wtd = weighted(tv);
+  // records merge into runs only with integer counters and no weights
+  const bool premerge = !kW;
   for (uint32_t p = tid; p <= P; p += kBinThreads) s_hist[p] = 0;
   __syncthreads();
 
   uint64_t key[kPer];
-  uint32_t pos[kPer];  // partition << 16 | rank, then the slot in the sorted tile; ~0 if unused
+  // partition << 16 | rank, then the entry's position in the sorted tile
+  // (for a merged record: its run head's); ~0 if the record has no entry
+  uint32_t pos[kPer];
   float rgb[kPer][3];
   uint32_t n_skip = 0, n_ovf = 0;
-  // with weights, two flags of a staged record ride in the top bits of its
-  // position (partition < 2^13 before the scan, position < 2^14 after it):
-  // staged for lookup only, and counted as a coordinate overflow
-  constexpr uint32_t kPosLookupOnly = 1u << 31, kPosOverflow = 1u << 30, kPosBits = kPosOverflow - 1;
+  // flags riding in the top bits of a position (partition < 2^13 before the
+  // scan, position < 2^14 after it): merged into the previous lane's entry;
+  // with weights, staged for lookup only and counted as a coordinate overflow
+  constexpr uint32_t kPosTail = 1u << 29, kPosLookupOnly = 1u << 31, kPosOverflow = 1u << 30;
+  constexpr uint32_t kPosBits = kPosTail - 1;
   const bool hr = rec.rough != nullptr;
   // Every load is unconditional (indices past the end are clamped, absent
   // arrays alias the positions) so that a batch of records is a single
@@ -125,7 +169,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   const float* p_oy = hr ? rec.oy : rec.px;
   const float* p_oz = hr ? rec.oz : rec.px;
   const float* p_ro = hr ? rec.rough : rec.px;
-  constexpr uint32_t kLoad = 4;
+  constexpr uint32_t kLoad = kPer == 12 ? 3 : 4;  // records per load round trip (12: no spills)
 #pragma unroll
   for (uint32_t j0 = 0; j0 < kPer; j0 += kLoad) {
     float f[kLoad][13];
@@ -152,28 +196,66 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint32_t j = j0 + q;
-      pos[j] = ~0u;
       const uint64_t i = t0 + (uint64_t)j * kBinThreads + tid;
-      if (i >= n) continue;
       bool ovf = false;
-      uint64_t k;
-      const bool kv = cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
-                               f[q][7], f[q][8], hr, f[q][12], kFp, fp[q], k, ovf);
+      uint64_t k = 0;
+      const bool kv = i < n && cell_key(kp, f[q][0], f[q][1], f[q][2], f[q][3], f[q][4], f[q][5], f[q][6],
+                                        f[q][7], f[q][8], hr, f[q][12], kFp, fp[q], k, ovf);
       const bool sv = finite3(f[q][9], f[q][10], f[q][11]);
-      if (!(kv && sv)) ++n_skip;
-      // a record whose sample is rejected but whose key is valid is still a
-      // query vertex: with the fused query it is staged for lookup only
-      if (!kv || (!sv && !pv.perm)) continue;
-      n_ovf += (ovf && sv) ? 1u : 0u;
-      const uint32_t p = partition_of(fmix64(k), tv.log2_slots, tv.part_log2);
-      const uint32_t rank = atomicAdd(&s_hist[p], 1u);
-      key[j] = sv ? k : k | kLookupOnlyBit;
-      pos[j] = (p << 16) | rank;
-      if (kW) pos[j] |= (sv ? 0u : kPosLookupOnly) | ((ovf && sv) ? kPosOverflow : 0u);
+      key[j] = (kv && sv) ? k : k | kLookupOnlyBit;
       rgb[j][0] = f[q][9];
       rgb[j][1] = f[q][10];
       rgb[j][2] = f[q][11];
+      if (i < n && !(kv && sv)) ++n_skip;
+      n_ovf += (kv && sv && ovf) ? 1u : 0u;
+      // a record whose sample is rejected but whose key is valid is still a
+      // query vertex: with the fused query it is staged for lookup only
+      const bool entry = kv && (sv || pv.perm);
+      pos[j] = entry ? ((kv && sv) ? 0u : kPosLookupOnly) | ((ovf && sv) ? kPosOverflow : 0u) : ~0u;
     }
+  }
+  // entries per partition (ranks), after merging runs of one cell in
+  // neighbouring lanes: only a run's head gets an entry
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const bool smp = pos[j] != ~0u && !(pos[j] & kPosLookupOnly);
+    bool tail = false;
+    if (premerge) {
+      // a sample whose key equals the previous lane's (also a sample)
+      // continues that lane's run
+      const unsigned long long kprev = shfl_up_u64(key[j], 1);
+      const bool sprev = __shfl_up((int)smp, 1) != 0;
+      tail = lane > 0 && smp && sprev && key[j] == kprev;
+      const unsigned long long cont = __ballot(tail);
+      if (lane == 0) s_cont[wave][j] = cont;
+      if (cont) {
+        // segmented suffix sums: after the step of offset d a lane holds
+        // the sum over itself and the next 2d - 1 lanes of its run, so each
+        // head ends with its run's total (fixed order: reproducible)
+        unsigned long long live = cont;  // lanes ending runs of >= 2d
+        for (uint32_t d = 1; live; d <<= 1) {
+          const float vr = __shfl_down(rgb[j][0], d);
+          const float vg = __shfl_down(rgb[j][1], d);
+          const float vb = __shfl_down(rgb[j][2], d);
+          const bool same = lane + d < 64 &&
+                            ((cont >> (lane + 1)) & ((1ull << d) - 1ull)) == ((1ull << d) - 1ull);
+          if (same) {
+            rgb[j][0] += vr;
+            rgb[j][1] += vg;
+            rgb[j][2] += vb;
+          }
+          live &= live >> d;
+        }
+      }
+    }
+    if (pos[j] == ~0u) continue;
+    if (tail) {
+      pos[j] = kPosTail;
+      continue;
+    }
+    const uint32_t p = partition_of(fmix64(key[j] & ~kLookupOnlyBit), tv.log2_slots, tv.part_log2);
+    const uint32_t rank = atomicAdd(&s_hist[p], 1u);
+    pos[j] |= (p << 16) | rank;
   }
   // rare-event counters: one atomic per wave when non-zero (with weights,
   // after the staging pass has judged them)
@@ -195,9 +277,18 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   for (uint32_t p = tid; p <= P; p += kBinThreads) offs[p] = s_hist[p];
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j) {
-    if (pos[j] == ~0u) continue;
-    const uint32_t q = pos[j] & kPosBits;
-    pos[j] = (s_hist[q >> 16] + (q & 0xffffu)) | (pos[j] & ~kPosBits);
+    if (pos[j] != ~0u && !(pos[j] & kPosTail)) {
+      const uint32_t q = pos[j] & ((1u << 29) - 1u);
+      pos[j] = (s_hist[q >> 16] + (q & 0xffffu)) | (pos[j] & ~((1u << 29) - 1u));
+    }
+    if (premerge && pv.perm) {
+      // a merged record is answered from its run head's entry
+      const unsigned long long cont = s_cont[wave][j];
+      if (cont) {
+        const uint32_t hp = (uint32_t)__shfl((int)pos[j], (int)run_head(cont, lane));
+        if (pos[j] == kPosTail) pos[j] = (hp & kPosBits) | kPosTail;
+      }
+    }
   }
   if (pv.perm) {
 #pragma unroll
@@ -208,42 +299,73 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   }
   __syncthreads();  // the histogram is dead from here on; its LDS becomes staging
 
-#pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j)
-    if (pos[j] != ~0u) s_k[pos[j] & kPosBits] = key[j];
-  __syncthreads();
-  for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_key[t0 + i] = s_k[i];
-  __syncthreads();
-#pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j) {
-    if (pos[j] == ~0u) continue;
-    const uint32_t o = 3 * (pos[j] & kPosBits);
-    s_f[o + 0] = rgb[j][0];
-    s_f[o + 1] = rgb[j][1];
-    s_f[o + 2] = rgb[j][2];
-  }
-  __syncthreads();
-  float* dst = pv.stage_rgb + 3 * t0;
-  for (uint32_t i = tid; i < 3 * count; i += kBinThreads) dst[i] = s_f[i];
+  auto own_entry = [&](uint32_t j) { return pos[j] != ~0u && !(pos[j] & kPosTail); };
+  // n of each entry: the records it carries (with weights: the record's
+  // weight); 0 marks an entry staged for lookup only
+  auto entry_n = [&](uint32_t j) {
+    uint32_t c = 1;
+    if (premerge) {
+      const unsigned long long cont = s_cont[wave][j];
+      if (cont) c = run_records(cont, lane);
+    }
+    return (pos[j] & kPosLookupOnly) ? 0u : c;
+  };
+  float wn[kW ? kPer : 1];
   if (kW) {
-    // The weights are first read here.  A staged sample whose weight is not
-    // finite and > 0 is rejected: counted as skipped (not as a coordinate
-    // overflow), and the merge pass, seeing the weight, does not accumulate
-    // it (with the fused query it is still looked up).
-    __syncthreads();
+    // The weights are first read here.  A sample whose weight is not finite
+    // and > 0 is rejected: counted as skipped (not as a coordinate
+    // overflow) and staged with n = 0, so the merge pass only looks it up
+    // (with the fused query) or ignores it; an accepted one is staged as
+    // w (r, g, b) with n = w.
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      if (pos[j] == ~0u) continue;
+      wn[j] = 0.0f;
+      if (!own_entry(j)) continue;
       const float w = rec.weight[t0 + (uint64_t)j * kBinThreads + tid];
-      s_f[pos[j] & kPosBits] = w;
-      if (!(pos[j] & kPosLookupOnly) && !(__builtin_isfinite(w) && w > 0.0f)) {
+      if (pos[j] & kPosLookupOnly) continue;
+      if (__builtin_isfinite(w) && w > 0.0f) {
+        rgb[j][0] *= w;
+        rgb[j][1] *= w;
+        rgb[j][2] *= w;
+        wn[j] = w;
+      } else {
         ++n_skip;
         n_ovf -= (pos[j] & kPosOverflow) ? 1u : 0u;
       }
     }
-    __syncthreads();
-    for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_w[t0 + i] = s_f[i];
     count_events();
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (own_entry(j)) s_k[pos[j] & kPosBits] = key[j];
+  __syncthreads();
+  for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_key[t0 + i] = s_k[i];
+  __syncthreads();
+  // the entries' values {r, g, b, n}: as float4 when they fit in the LDS,
+  // else in two halves, (r, g) then (b, n)
+  auto entry_w = [&](uint32_t j) { return kW ? wn[kW ? j : 0] : (float)entry_n(j); };
+  const size_t lds_bytes = (size_t)kBinThreads * kPer * bin_lds_per_record(kPer);  // the launch's dynamic LDS
+  if ((size_t)count * 16 <= lds_bytes) {
+    float4* s_v = reinterpret_cast<float4*>(s_dyn_bin);
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j)
+      if (own_entry(j)) s_v[pos[j] & kPosBits] = make_float4(rgb[j][0], rgb[j][1], rgb[j][2], entry_w(j));
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += kBinThreads) pv.stage_v[t0 + i] = s_v[i];
+  } else {
+    float2* s_v = reinterpret_cast<float2*>(s_dyn_bin);
+    float2* dst = reinterpret_cast<float2*>(pv.stage_v + t0);
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j)
+      if (own_entry(j)) s_v[pos[j] & kPosBits] = make_float2(rgb[j][0], rgb[j][1]);
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += kBinThreads) dst[2 * i] = s_v[i];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j)
+      if (own_entry(j)) s_v[pos[j] & kPosBits] = make_float2(rgb[j][2], entry_w(j));
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += kBinThreads) dst[2 * i + 1] = s_v[i];
   }
 }
 
@@ -473,24 +595,21 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 
   const uint32_t batches = for_each_batch([&](const uint64_t* at, const bool* ev, uint32_t nb) {
     unsigned long long ek[kEntryBatch];
-    float er[kEntryBatch], eg[kEntryBatch], eb[kEntryBatch], ew[kEntryBatch];
+    float4 v[kEntryBatch];
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       ek[q] = pv.stage_key[at[q]];
-      er[q] = pv.stage_rgb[3 * at[q]];
-      eg[q] = pv.stage_rgb[3 * at[q] + 1];
-      eb[q] = pv.stage_rgb[3 * at[q] + 2];
-      ew[q] = pv.stage_w ? pv.stage_w[at[q]] : 1.0f;
+      v[q] = pv.stage_v[at[q]];
     }
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       uint32_t slot = ~0u;
-      // a staged weight that is not finite and > 0 rejects the sample: with
-      // the fused query the entry is only looked up, else it is ignored
-      const bool wbad = pv.stage_w && !(__builtin_isfinite(ew[q]) && ew[q] > 0.0f);
-      const bool lookup_only = results && ((ek[q] & kLookupOnlyBit) != 0 || wbad);
-      if (lookup_only) slot = kLookupLater;
-      if (ev[q] && !lookup_only && !wbad) {
+      // n = 0: an entry staged for lookup only (a rejected sample); with the
+      // fused query it is looked up after the blend, else it is ignored
+      if (results && v[q].w == 0.0f) slot = kLookupLater;
+      if (ev[q] && v[q].w != 0.0f) {
+        // records behind the entry, for the drop and probe statistics
+        const uint32_t recs = pv.weights ? 1u : (uint32_t)v[q].w;
         const unsigned long long key = ek[q];
         const uint32_t start = (uint32_t)fmix64(key) & (B - 1);
         uint32_t i = 0;
@@ -504,24 +623,16 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           }
         }
         if (slot == ~0u) {
-          atomicAdd(&s_dropped, 1u);
+          atomicAdd(&s_dropped, recs);
         } else {
-          if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], 1u);
+          if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], recs);
           if (wtd)
-            atomicAdd(reinterpret_cast<float*>(&s_cnt[slot]), ew[q]);
+            atomicAdd(reinterpret_cast<float*>(&s_cnt[slot]), v[q].w);
           else
-            atomicAdd(&s_cnt[slot], 1u);
-          if (pv.stage_w) {
-            // w * value exactly (binary64 holds the product of two binary32)
-            const double dw = (double)ew[q];
-            atomicAdd(&s_sum0[slot], (double)er[q] * dw);
-            atomicAdd(&s_sum1[slot], (double)eg[q] * dw);
-            atomicAdd(&s_sum2[slot], (double)eb[q] * dw);
-          } else {
-            atomicAdd(&s_sum0[slot], (double)er[q]);
-            atomicAdd(&s_sum1[slot], (double)eg[q]);
-            atomicAdd(&s_sum2[slot], (double)eb[q]);
-          }
+            atomicAdd(&s_cnt[slot], (uint32_t)v[q].w);
+          atomicAdd(&s_sum0[slot], (double)v[q].x);
+          atomicAdd(&s_sum1[slot], (double)v[q].y);
+          atomicAdd(&s_sum2[slot], (double)v[q].z);
         }
       }
       if (results) {
@@ -633,7 +744,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       }
       return ~0u;
     };
-    // the value a lookup of the cell in slot returns (kDroppedBits if none)
+    // the value a lookup of the cell in slot returns (kDroppedBits if none),
+    // written over the entry in one 16-byte store
     auto put = [&](uint64_t at, uint32_t slot) {
       float v[3] = {__uint_as_float(kDroppedBits), 0.0f, 0.0f};
       if (slot != ~0u && s_cnt[slot] > 0) {
@@ -645,10 +757,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         const Slot sl = tv.slots[base + slot];
         if (sl.c_old > 0) load_state(sl, bp.dtype, v[0], v[1], v[2]);
       }
-      float* d = pv.stage_rgb + 3 * at;
-      d[0] = v[0];
-      d[1] = v[1];
-      d[2] = v[2];
+      pv.stage_v[at] = make_float4(v[0], v[1], v[2], 0.0f);
     };
 #pragma unroll
     for (uint32_t b = 0; b < kKeepBatches; ++b) {
@@ -720,12 +829,14 @@ __device__ __forceinline__ void unstage_body(const PartView& pv, uint32_t P, uin
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint64_t t0 = (uint64_t)t * pv.tile;
   const uint32_t count = pv.runs[(uint64_t)t * (P + 1) + P];
-  // t0 * 12 bytes is a multiple of 16 (tiles are multiples of 512 records)
-  const float4* src4 = reinterpret_cast<const float4*>(pv.stage_rgb + 3 * t0);
-  const uint32_t nf = 3 * count, n4 = nf / 4;
-  float4* dst4 = reinterpret_cast<float4*>(s_res);
-  for (uint32_t i = tid; i < n4; i += nt) dst4[i] = src4[i];
-  for (uint32_t i = 4 * n4 + tid; i < nf; i += nt) s_res[i] = pv.stage_rgb[3 * t0 + i];
+  // the answers (r, g, b of each 16-byte entry) packed into LDS
+  const float4* src = pv.stage_v + t0;
+  for (uint32_t i = tid; i < count; i += nt) {
+    const float4 v = src[i];
+    s_res[3 * i] = v.x;
+    s_res[3 * i + 1] = v.y;
+    s_res[3 * i + 2] = v.z;
+  }
   __syncthreads();
   const uint64_t end = t0 + pv.tile < n ? t0 + pv.tile : n;
   const bool vec = (n & 3u) == 0 && ((uintptr_t)out & 15u) == 0 && ((uintptr_t)found & 3u) == 0;
@@ -769,7 +880,7 @@ __global__ void __launch_bounds__(kUnstageThreads) k_unstage(PartView pv, uint32
 
 // ------------------------------------------------------------------ launchers
 static size_t bin_lds(uint32_t P, uint32_t per) {
-  const size_t hist = (size_t)(P + 1) * 4, stage = (size_t)kBinThreads * per * 12;
+  const size_t hist = (size_t)(P + 1) * 4, stage = (size_t)kBinThreads * per * bin_lds_per_record(per);
   return hist > stage ? hist : stage;
 }
 
@@ -841,7 +952,7 @@ hipError_t launch_bin(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = bin_lds(P, per);
   const uint32_t x = record_extras(rec);
-  if ((x & kXWeight) && (!pv.stage_w || !weighted(tv))) return hipErrorInvalidValue;
+  if ((x & kXWeight) && !weighted(tv)) return hipErrorInvalidValue;
   if (per == 8) return launch_bin_x<8>(x, rec, n, kp, tv, pv, shm, ntiles, s);
   if (per == 12) return launch_bin_x<12>(x, rec, n, kp, tv, pv, shm, ntiles, s);
   return launch_bin_x<16>(x, rec, n, kp, tv, pv, shm, ntiles, s);
@@ -1051,7 +1162,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
       lds_q = unstage_lds(S.pv.tile);
     }
     const uint32_t xs = record_extras(S.rec);
-    if ((xs & kXWeight) && (!S.pv.stage_w || !weighted(S.tv))) return hipErrorInvalidValue;
+    if ((xs & kXWeight) && !weighted(S.tv)) return hipErrorInvalidValue;
     x |= xs;
     tiles += S.ntiles;
     parts += (S.nparts + 7u) & ~7u;
