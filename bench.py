@@ -36,14 +36,18 @@ def _workload(name):
     return {"plain": W.plain, "tiny": W.tiny, "precision": W.precision}[name]()
 
 
-def algorithmic_bytes(n, c):
+def algorithmic_bytes(n, c, state_bytes=4):
     """Bytes the method must move per iteration for n records (queries = n)
-    touching c distinct cells, split by kernel kind."""
+    touching c distinct cells, split by kernel kind.  With 16-bit state
+    (state_bytes 2) a cell's update reads and writes 6 bytes of approximant
+    instead of 12 and a lookup reads 6 instead of 12."""
+    upd = CELL_UPDATE - 2 * 3 * (4 - state_bytes)
+    qry = CELL_QUERY - 3 * (4 - state_bytes)
     return {
         "bin": n * REC_BYTES,
-        "merge_blend": c * (CELL_INSERT + CELL_UPDATE),
-        "query": n * QRY_BYTES + c * CELL_QUERY,
-        "iteration": n * (REC_BYTES + QRY_BYTES) + c * (CELL_INSERT + CELL_UPDATE + CELL_QUERY),
+        "merge_blend": c * (CELL_INSERT + upd),
+        "query": n * QRY_BYTES + c * qry,
+        "iteration": n * (REC_BYTES + QRY_BYTES) + c * (CELL_INSERT + upd + qry),
     }
 
 
@@ -70,12 +74,10 @@ def measured_traffic(workload: str, kernel: str):
     return int(hits[0]["bytes"]) if len(hits) == 1 else None
 
 
-def cpu_baseline(wl, rec, budget_s):
-    """The oracle as it stands, single-threaded, on whole iterations of the
-    same records until the time budget is used (at least one iteration)."""
-    import oracle
+def _oracle_rate(orc, rec, budget_s):
+    """Whole iterations (insert, update, query) of rec on orc until the time
+    budget is used (at least one); returns (records/s, iterations, seconds)."""
     n = len(rec["px"])
-    orc = oracle.Oracle(**wl["table"])
     t0 = time.perf_counter()
     done = 0
     while True:
@@ -84,13 +86,25 @@ def cpu_baseline(wl, rec, budget_s):
         orc.query(rec)
         done += 1
         el = time.perf_counter() - t0
-        if el >= budget_s:
+        if el >= budget_s or el / done * (done + 1) > budget_s * 1.5:
             break
-        if el / done * (done + 1) > budget_s * 1.5:
-            break
-    return {"value": n * done / el, "unit": "vertex records/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} whole iteration(s) (insert+update+query) of {n} records of the "
-                      f"{wl['name']} workload, single thread, {el:.1f} s",
+    return n * done / el, done, el
+
+
+def cpu_baseline(wl, rec, budget_s):
+    """The oracle as it stands on the host cores: the key-sharded variant on
+    every host thread (the headline value) and the single-threaded oracle,
+    each on whole iterations of the same records within its time budget."""
+    import oracle
+    n = len(rec["px"])
+    threads = max(1, min(16, os.cpu_count() or 1))
+    many, done_m, el_m = _oracle_rate(oracle.ShardedOracle(threads, **wl["table"]), rec, budget_s)
+    one, done_1, el_1 = _oracle_rate(oracle.Oracle(**wl["table"]), rec, budget_s / 2)
+    return {"value": round(many, 1), "unit": "vertex records/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done_m} whole iteration(s) (insert+update+query) of {n} records of the "
+                      f"{wl['name']} workload, key-sharded oracle on {threads} host threads, {el_m:.1f} s",
+            "single_thread": {"value": round(one, 1), "cores": 1,
+                              "sample": f"{done_1} whole iteration(s) of the same records, {el_1:.1f} s"},
             "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
 
 
@@ -134,40 +148,69 @@ def with_params(cfg: dict, params: dict, flags: int = 0) -> dict:
     return c
 
 
-def form_precision(torch, psf, W, iters=12):
-    """Precision workload (1920x1080, 5 vertices, HDR): records/s of the fused
-    iteration for FP32, FP16 and BF16 approximant storage."""
+PRECISION_STATES = (("f32", 0), ("f16", 1), ("bf16", 2), ("f16_ef", 3), ("bf16_ef", 4))
+
+
+def form_precision(torch, psf, W, iters=64, pool=16):
+    """Precision workload (1920x1080, 5 vertices, HDR lognormal(0, 2), 2^24
+    slots): the config's 64 iterations on a fresh table per state format
+    (FP32; FP16 and BF16 re-rounded every blend; both with the FP32
+    rounding residual carried), frames cycled from a pool of 16 distinct
+    iterations resident in HBM.  A second pass of the same length brackets
+    every kernel with HIP events for the per-kernel times and the roofline."""
     import numpy as np
     wl = W.precision()
     sc = W.make_scene(wl)
     n = W.records_per_iteration(wl)
-    frames = [_dev(sc.generate(wl["gen"], i), torch) for i in range(2)]
+    frames = [_dev(sc.generate(wl["gen"], i), torch) for i in range(pool)]
+    params = tuned(wl["name"])
+    o = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    f = torch.empty(n, dtype=torch.uint8, device="cuda")
     out = {}
-    for name in ("f32", "f16", "bf16"):
-        t = psf.Table(**dict(with_params(wl["table"], tuned(wl["name"])), max_batch=n,
-                             state_dtype={"f32": 0, "f16": 1, "bf16": 2}[name]))
-        o = torch.empty((3, n), dtype=torch.float32, device="cuda")
-        f = torch.empty(n, dtype=torch.uint8, device="cuda")
-        for i in range(2):
-            t.iterate(frames[i % 2], out=o, found=f)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(iters)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(iters):
-            ev[k][0].record()
-            t.iterate(frames[k % 2], out=o, found=f)
-            ev[k][1].record()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ms = np.array([a.elapsed_time(b) for a, b in ev])
-        st = t.stats()
-        out[name] = {"records_per_s": round(n * iters / el, 1), "ms_per_iter": round(el / iters * 1e3, 4),
-                     "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
-                     "saturated": st["saturated"], "dropped": st["dropped"]}
-        t.close()
-    return {"workload": wl["name"], "records_per_iteration": n, "params": tuned(wl["name"]), "by_state": out,
-            "note": "error vs the binary64 oracle is asserted in tests/test_gpu_precision.py"}
+    for name, code in PRECISION_STATES:
+        res = {}
+        for flags in (0, psf.PSF_FLAG_TIMING):
+            t = psf.Table(**dict(with_params(wl["table"], params, flags), max_batch=n, state_dtype=code))
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(iters)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(iters):
+                ev[k][0].record()
+                t.iterate(frames[k % pool], out=o, found=f)
+                ev[k][1].record()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st = t.stats()
+            if flags:
+                kt = {k: {"launches": v[0], "avg_ms": round(v[1] / max(1, v[0]), 5)}
+                      for k, v in t.kernel_times().items()}
+                touched = st["touched_total"] / max(1, st["updates"])
+                ab = algorithmic_bytes(n, touched, state_bytes=4 if code == 0 else 2)
+                dom = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches"])
+                ach = ab.get(dom, 0) / (kt[dom]["avg_ms"] * 1e-3) / 1e9
+                res.update({"kernels": kt, "cells_touched_per_iteration": int(touched),
+                            "algorithmic_bytes_per_iteration": int(ab["iteration"]),
+                            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
+                                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                         "algorithmic_bytes_per_launch": int(ab.get(dom, 0)),
+                                         "avg_launch_ms": kt[dom]["avg_ms"]}})
+            else:
+                ms = np.array([a.elapsed_time(b) for a, b in ev])
+                res.update({"records_per_s": round(n * iters / el, 1), "ms_per_iter": round(el / iters * 1e3, 4),
+                            "p50_iter_ms": round(float(np.percentile(ms, 50)), 4),
+                            "p99_iter_ms": round(float(np.percentile(ms, 99)), 4),
+                            "saturated": st["saturated"], "dropped": st["dropped"]})
+            t.close()
+        touched = res["cells_touched_per_iteration"]
+        res["iteration_hbm_frac"] = round(algorithmic_bytes(n, touched, state_bytes=4 if code == 0 else 2)
+                                          ["iteration"] / (res["ms_per_iter"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[name] = res
+    del frames
+    return {"workload": wl["name"], "records_per_iteration": n, "iterations": iters,
+            "frames": f"{pool} distinct iterations resident in HBM, cycled", "params": params,
+            "by_state": out,
+            "note": "error vs the binary64 oracle over all 64 iterations is asserted in tests/test_gpu_precision.py"}
 
 
 def form_batched(torch, psf, W, iters=8, sessions=16):
@@ -302,40 +345,75 @@ def form_estimate(torch, psf, W, iters=32, warm_frames=4):
     return res
 
 
-def form_progressive(torch, psf, W, iters=16, paths=921600, verts=4):
-    """The progressive solver's feedback loop (Sec. 2.2) in the closed
-    furnace: every frame looks up the previous approximant at each path's
-    next vertex, forms L_e + L~ * f G w / p and inserts and blends it."""
+def form_progressive(torch, psf, W, iters=16, width=1280, height=720, verts=4):
+    """The progressive solver with its path sampler on the GPU (Sec. 2.2;
+    Algorithm 2 with next-event estimation): every frame psf_sample_paths
+    traces one path per pixel through the tiny workload's box (emitter under
+    the ceiling; camera inside the box so every pixel sees it) and
+    psf_progressive_step looks up the previous approximant at each path's
+    next vertex, forms the samples, inserts and blends them -- nothing
+    leaves the device.  Also: the closed furnace run to convergence the same
+    way, against rho L_e / (1 - rho)."""
     import numpy as np
-    cfg = dict(W.furnace_table(log2_slots=20), flags=psf.PSF_FLAG_TIMING)
-    n = paths * verts
+    prims, _ = W.box_scene()
+    scene = psf.Scene(prims)
+    cam = psf.camera((0.5, 0.5, 0.02), (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), 60.0, width, height, 1)
+    n = width * height * verts
+    cfg = dict(W.tiny()["table"], log2_slots=22, flags=psf.PSF_FLAG_TIMING, cam=(0.5, 0.5, 0.02),
+               kappa=W.kappa_for(60.0, height, 4.0, -10), e_min=-10)
     t = psf.Table(**dict(cfg, max_batch=n))
-    frames = []
-    for it in range(2):
-        x, nx, tp, em = W.furnace_paths(paths, verts, it)
-        frames.append((_dev(x, torch), _dev(nx, torch),
-                       tuple(torch.from_numpy(a).cuda() for a in tp), tuple(torch.from_numpy(a).cuda() for a in em)))
-    out = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    samples = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    buf = None
+
+    def frame(k):
+        nonlocal buf
+        x, nx, tp, le = psf.sample_paths(scene, cam, verts, psf.PSF_PATHS_LOE, psf.PSF_ORIGIN_CAMERA, seed=17,
+                                         frame=k, out=buf)
+        if buf is None:
+            buf = dict(x, qx=nx["px"], qy=nx["py"], qz=nx["pz"], qnx=nx["nx"], qny=nx["ny"], qnz=nx["nz"],
+                       qox=nx["ox"], qoy=nx["oy"], qoz=nx["oz"], qrough=nx["rough"], t_r=tp[0], t_g=tp[1],
+                       t_b=tp[2], le_r=le[0], le_g=le[1], le_b=le[2])
+        return x, nx, tp, le
+
     for k in range(4):
-        f = frames[k % 2]
-        t.progressive_step(f[0], f[1], f[2], f[3], out=out)
+        x, nx, tp, le = frame(k)
+        t.progressive_step(x, nx, tp, le, out=samples)
     torch.cuda.synchronize()
     t.kernel_times(reset=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
     t0 = time.perf_counter()
     for k in range(iters):
-        f = frames[k % 2]
-        t.progressive_step(f[0], f[1], f[2], f[3], out=out)
+        ev[k][0].record()
+        x, nx, tp, le = frame(4 + k)
+        ev[k][1].record()
+        t.progressive_step(x, nx, tp, le, out=samples)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kt = {k: round(v[1] / max(1, v[0]), 5) for k, v in t.kernel_times().items()}
-    L = t.export()["L"]
-    le, rho = np.array([1.0, 0.5, 0.25]), np.array([0.5, 0.6, 0.7])
-    rel = np.abs(L / (le / (1.0 - rho))[:, None] - 1.0)
-    res = {"scene": "closed furnace (unit sphere, L_e (1, 0.5, 0.25), albedo (0.5, 0.6, 0.7))",
-           "paths": paths, "vertices_per_path": verts, "records_per_s": round(n * iters / el, 1),
-           "ms_per_frame": round(el / iters * 1e3, 4), "kernels_avg_ms": kt,
-           "mean_rel_error_to_closed_form": round(float(rel.mean()), 6), "frames_run": iters + 4}
+    kt["sample_paths"] = round(float(np.mean([a.elapsed_time(b) for a, b in ev])), 5)
+    st = t.stats()
+    res = {"scene": "box of the tiny workload with a 0.5 x 0.5 emitter, camera inside, Algorithm 2 with NEE",
+           "paths": width * height, "vertices_per_path": verts, "records_per_frame": n,
+           "records_per_s": round(n * iters / el, 1), "ms_per_frame": round(el / iters * 1e3, 4),
+           "kernels_avg_ms": kt, "skipped_per_frame": st["skipped"] // (iters + 4), "dropped": st["dropped"],
+           "frames_run": iters + 4}
     t.close()
+    # the closed furnace, every frame sampled and filtered on the device
+    le_f, rho = np.array([1.0, 0.5, 0.25]), np.array([0.5, 0.6, 0.7])
+    fs = psf.Scene(W.furnace_scene(tuple(le_f), tuple(rho)))
+    fcam = psf.camera((0, 0, 0), (0, 0, 1), (0, 1, 0), 60.0, 65536, 1)
+    ft = psf.Table(**W.furnace_table())
+    for k in range(200):
+        x, nx, tp, le = psf.sample_paths(fs, fcam, 2, psf.PSF_PATHS_LOE, psf.PSF_ORIGIN_POINT, seed=23, frame=k)
+        ft.progressive_step(x, nx, tp, le)
+    L = ft.export()["L"].astype(np.float64)
+    want = (rho * le_f / (1.0 - rho))[:, None]
+    rel = np.abs(L / want - 1.0)
+    res["furnace"] = {"frames": 200, "paths_per_frame": 65536, "vertices_per_path": 2,
+                      "field": "L_o minus emission (Algorithm 2, NEE + balance heuristic)",
+                      "mean_rel_error_to_closed_form": round(float(rel.mean()), 7),
+                      "p90_rel_error": round(float(np.percentile(rel, 90)), 7)}
+    ft.close()
     return res
 
 
@@ -380,27 +458,27 @@ def form_weighted(torch, psf, W, iters=16):
     return res
 
 
-def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
+def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0, frames_per_session=3):
     """Poisson arrivals at 20/s, resolutions lognormal around 720p, 32-128
     iterations each, 1 spp, 4 vertices; continuous batching under an HBM
-    budget.  Frames come from per-resolution-class pools in HBM."""
+    budget.  Every session renders a scene of its own (seeded by the
+    session, diffuse-only or half glossy) and cycles through frames of its
+    own distinct iterations, resident in HBM before the run."""
     from paper_2005_07547_amd import serving
     from synth import Scene
     draws = serving.draw_requests(n_sessions, rate=rate, seed=5)
-    pools = {}
     reqs = []
     wl = W.plain()
     for sid, arrival, cls, iters, seed in draws:
         w, h = serving.RES_CLASSES[cls]
-        if cls not in pools:
-            gen = dict(wl["gen"], width=w, height=h, seed=700 + cls)
-            sc = Scene(Scene.RANDOM, seed=700 + cls, glossy_frac=-1.0 if cls % 2 else 0.5)
-            pools[cls] = [_dev(sc.generate(gen, f), torch) for f in range(2)]
+        gen = dict(wl["gen"], width=w, height=h, seed=seed)
+        sc = Scene(Scene.RANDOM, seed=seed, glossy_frac=-1.0 if sid % 2 else 0.5)
+        frames = [_dev(sc.generate(gen, f), torch) for f in range(frames_per_session)]
         log2 = int(min(25, max(16, math.ceil(math.log2(w * h * 4)) + 1)))
         cfg = dict(wl["table"], log2_slots=log2,
                    kappa=W.kappa_for(60.0, h, 8.0 * math.sqrt(2.0), -5))
         reqs.append(serving.SessionRequest(sid=sid, arrival=arrival, iterations=iters, table_cfg=cfg,
-                                           frames=pools[cls], records=w * h * 4))
+                                           frames=frames, records=w * h * 4))
     srv = serving.Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=64)
     summ = srv.run(reqs, time_limit=240)
     summ = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
@@ -441,6 +519,8 @@ def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0):
     summ["plain_one_session_after_another"] = {"records_per_s": round(done / plain_el, 1),
                                                "wall_s": round(plain_el, 4)}
     summ["speedup_served_over_plain"] = round(sat["records_per_s"] / (done / plain_el), 3)
+    summ["frames"] = (f"a scene per session, {frames_per_session} distinct iterations per session cycled, "
+                      "resident in HBM")
     return summ
 
 

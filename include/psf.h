@@ -430,6 +430,86 @@ psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_estimate_ar
                         int32_t mode, float param, float* d_out_rgb, uint8_t* d_out_applied,
                         psf_stream stream);
 
+/* Path sampler for the progressive solver (Sec. 2.2, Eq. 7-9; Algorithms 1
+ * and 2): the step upstream of the hash path, on the GPU.  Traces one path
+ * of `verts` vertices x_1..x_V per pixel sample through a scene of quads
+ * and spheres with Lambertian materials and writes, per vertex (depth-major:
+ * vertex 1 of every path, then vertex 2, ...; n = paths * verts entries per
+ * array, caller-owned device memory), what one solver frame consumes:
+ *   x        the vertex as a record: position, normal (facing the outgoing
+ *            direction), outgoing direction omega_o = -omega_i of the step
+ *            that reached it, roughness (of its primitive);
+ *   next     its next vertex x_{i+1} as a query (NaN position where the
+ *            path left the scene: its lookup finds nothing);
+ *   t        the throughput factor f G w / p of the sampled step x_i ->
+ *            x_{i+1} (cosine-weighted scattering: the albedo; 0 after an
+ *            escape);
+ *   le       the emission argument of psf_progressive_step:
+ *              PSF_PATHS_LO  (Algorithm 1, field L_o):   L_e(x_i);
+ *              PSF_PATHS_LOE (Algorithm 2, field L_o\e): w_nee NEE(x_i) +
+ *                t_i w_bsdf L_e(x_{i+1}), next-event estimation toward a
+ *                uniformly chosen emitter (uniform point on it, shadow ray)
+ *                and the emission reached by the scattering event, combined
+ *                by the balance heuristic.
+ * So psf_sample_paths followed by psf_progressive_step(x, next, {le, t}) is
+ * one frame of the solver, entirely on the device.  A path that leaves the
+ * scene restarts from its origin (every path has exactly verts vertices).
+ * Random numbers: Philox-4x32-10 keyed (seed, frame) with counter (path,
+ * vertex, purpose, 0), so the output is a pure function of its inputs.
+ * Emitters emit on both sides of quads and outward from spheres, with
+ * radiance `emission` (uniform, Lambertian). */
+enum { PSF_PRIM_QUAD = 0, PSF_PRIM_SPHERE = 1 };
+enum { PSF_PATHS_LO = 0, PSF_PATHS_LOE = 1 };
+enum { PSF_ORIGIN_CAMERA = 0, PSF_ORIGIN_POINT = 1 };
+
+typedef struct psf_prim {
+  int32_t kind;        /* PSF_PRIM_* */
+  float p[3];          /* quad: centre; sphere: centre */
+  float u[3];          /* quad: half-edge vector (the quad is p + a u + b v,
+                          |a|, |b| <= 1); sphere: u[0] = radius */
+  float v[3];          /* quad: the other half-edge vector */
+  float albedo[3];     /* Lambertian reflectance, f = albedo / pi */
+  float emission[3];   /* emitted radiance (0 for no emitter) */
+  float rough;         /* reported as the vertex roughness (keys glossy
+                          vertices by direction); scattering is diffuse */
+} psf_prim;
+
+typedef struct psf_camera {
+  float pos[3];        /* origin of every path */
+  float fwd[3], up[3]; /* unit, orthogonal: view direction and image up */
+  float fov_y;         /* vertical field of view, radians, in (0, pi) */
+  uint32_t width, height, spp;  /* paths = width * height * spp, pixel =
+                                   path / spp in scanline order */
+} psf_camera;
+
+typedef struct psf_path_params {
+  uint32_t verts;      /* vertices per path, >= 1 */
+  int32_t mode;        /* PSF_PATHS_LO or PSF_PATHS_LOE */
+  int32_t origin;      /* PSF_ORIGIN_CAMERA: pinhole camera rays, jittered
+                          in the pixel; PSF_ORIGIN_POINT: uniform directions
+                          from cam.pos (a closed scene seen from inside) */
+  uint32_t seed, frame;
+} psf_path_params;
+
+typedef struct psf_path_out {
+  float *px, *py, *pz, *nx, *ny, *nz, *ox, *oy, *oz, *rough;          /* x_i */
+  float *qx, *qy, *qz, *qnx, *qny, *qnz, *qox, *qoy, *qoz, *qrough;   /* x_{i+1} */
+  float *t_r, *t_g, *t_b;                                             /* f G w / p */
+  float *le_r, *le_g, *le_b;                                          /* emission argument */
+} psf_path_out;
+
+/* d_prims: n_prims scene primitives in device memory (at most 4096; a
+ * kind other than PSF_PRIM_SPHERE is read as a quad).  INVALID_ARGUMENT for
+ * a NULL output array, verts = 0, an unknown mode or origin, a field of
+ * view outside (0, pi), an empty image or more than 2^32 paths. */
+psf_status psf_sample_paths(const psf_prim* d_prims, uint32_t n_prims, const psf_camera* cam,
+                            const psf_path_params* p, const psf_path_out* out, psf_stream stream);
+
+/* Philox-4x32-10 (Salmon et al., SC'11) on the device, as the path sampler
+ * uses it: out[4i..4i+3] = philox(ctr[4i..4i+3], key[2i..2i+1]) for i < n
+ * (device arrays); test support for the generator's known answers. */
+psf_status psf_philox(const uint32_t* d_ctr, const uint32_t* d_key, uint64_t n, uint32_t* d_out, psf_stream stream);
+
 /* Per-kernel timing (tables created with PSF_FLAG_TIMING): for each kernel
  * kind k < PSF_K_COUNT, launches[k] and total_ms[k] (host arrays of
  * PSF_K_COUNT entries) receive the launches recorded since the last reset

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libpsf.so")
-SOURCES = ["psf_api.hip", "psf_kernels.hip", "psf_partition.hip"]
+SOURCES = ["psf_api.hip", "psf_kernels.hip", "psf_partition.hip", "psf_paths.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

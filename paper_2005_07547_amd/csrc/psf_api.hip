@@ -935,6 +935,38 @@ PSF_API psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_est
   return e == hipSuccess ? PSF_OK : hip_fail(e, "estimate launch");
 }
 
+PSF_API psf_status psf_sample_paths(const psf_prim* d_prims, uint32_t n_prims, const psf_camera* cam,
+                                    const psf_path_params* p, const psf_path_out* out, psf_stream stream) {
+  if (!cam || !p || !out) return fail(PSF_INVALID_ARGUMENT, "camera, parameters or outputs are NULL");
+  if (n_prims > 4096) return fail(PSF_INVALID_ARGUMENT, "at most 4096 primitives");
+  if (n_prims > 0 && !d_prims) return fail(PSF_INVALID_ARGUMENT, "primitives are NULL");
+  if (p->verts == 0) return fail(PSF_INVALID_ARGUMENT, "verts must be >= 1");
+  if (p->mode != PSF_PATHS_LO && p->mode != PSF_PATHS_LOE) return fail(PSF_INVALID_ARGUMENT, "unknown mode");
+  if (p->origin != PSF_ORIGIN_CAMERA && p->origin != PSF_ORIGIN_POINT)
+    return fail(PSF_INVALID_ARGUMENT, "unknown origin");
+  if (cam->width == 0 || cam->height == 0 || cam->spp == 0) return fail(PSF_INVALID_ARGUMENT, "empty image");
+  if (!(cam->fov_y > 0.0f && cam->fov_y < 3.14159f)) return fail(PSF_INVALID_ARGUMENT, "fov_y must be in (0, pi)");
+  const uint64_t paths = (uint64_t)cam->width * cam->height * cam->spp;
+  if (paths > (1ull << 32)) return fail(PSF_INVALID_ARGUMENT, "more than 2^32 paths");
+  float* const arrays[] = {out->px,  out->py,  out->pz,  out->nx,  out->ny,  out->nz,   out->ox,
+                           out->oy,  out->oz,  out->rough, out->qx, out->qy, out->qz,  out->qnx,
+                           out->qny, out->qnz, out->qox, out->qoy, out->qoz, out->qrough, out->t_r,
+                           out->t_g, out->t_b, out->le_r, out->le_g, out->le_b};
+  for (float* a : arrays)
+    if (!a) return fail(PSF_INVALID_ARGUMENT, "an output array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = psf::launch_sample_paths(d_prims, n_prims, *cam, *p, paths, *out, s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "path sampler launch");
+}
+
+PSF_API psf_status psf_philox(const uint32_t* d_ctr, const uint32_t* d_key, uint64_t n, uint32_t* d_out,
+                              psf_stream stream) {
+  if (n == 0) return PSF_OK;
+  if (!d_ctr || !d_key || !d_out) return fail(PSF_INVALID_ARGUMENT, "arrays are NULL");
+  hipError_t e = psf::launch_philox(d_ctr, d_key, n, d_out, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "philox launch");
+}
+
 PSF_API psf_status psf_kernel_times(psf_table* t, uint64_t* launches, double* total_ms, int reset) {
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
   if (!t->timer) return fail(PSF_NOT_SUPPORTED, "table was created without PSF_FLAG_TIMING");

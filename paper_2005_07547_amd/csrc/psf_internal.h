@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "psf.h"
 #include "psf_device.h"
 
 namespace psf {
@@ -137,6 +138,18 @@ hipError_t launch_batch(const BatchSession* d_sessions, const uint32_t* d_begins
 // Threads of a batch query block: the lookup of kQueryBlock queries, or the
 // unstage of one fused session's tile (as wide as the single-table unstage).
 constexpr uint32_t kQueryBlock = 512;
+// Path sampler (the public structures, device copies in the kernels).
+using PathPrim = psf_prim;
+using PathCamera = psf_camera;
+using PathParams = psf_path_params;
+using PathOut = psf_path_out;
+constexpr int32_t kPrimSphere = PSF_PRIM_SPHERE;
+constexpr int32_t kOriginPoint = PSF_ORIGIN_POINT;
+constexpr int32_t kPathsLo = PSF_PATHS_LO, kPathsLoe = PSF_PATHS_LOE;
+hipError_t launch_sample_paths(const PathPrim* prims, uint32_t np, const PathCamera& cam, const PathParams& prm,
+                               uint64_t n_paths, const PathOut& out, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out, hipStream_t s);
+
 hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);

@@ -25,6 +25,9 @@ PSF_FLAG_TIMING = 2
 PSF_FLAG_TRANSPOSE_RUNS = 4
 PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
+PSF_PRIM_QUAD, PSF_PRIM_SPHERE = 0, 1
+PSF_PATHS_LO, PSF_PATHS_LOE = 0, 1
+PSF_ORIGIN_CAMERA, PSF_ORIGIN_POINT = 0, 1
 
 REC_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "r", "g", "b", "rough", "footprint",
               "weight")
@@ -86,6 +89,32 @@ class psf_session(ctypes.Structure):
     ]
 
 
+class psf_prim(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_float * 3), ("u", ctypes.c_float * 3),
+                ("v", ctypes.c_float * 3), ("albedo", ctypes.c_float * 3), ("emission", ctypes.c_float * 3),
+                ("rough", ctypes.c_float)]
+
+
+class psf_camera(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("fwd", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y", ctypes.c_float), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("spp", ctypes.c_uint32)]
+
+
+class psf_path_params(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_uint32), ("mode", ctypes.c_int32), ("origin", ctypes.c_int32),
+                ("seed", ctypes.c_uint32), ("frame", ctypes.c_uint32)]
+
+
+PATH_X = ("px", "py", "pz", "nx", "ny", "nz", "ox", "oy", "oz", "rough")
+PATH_NEXT = ("qx", "qy", "qz", "qnx", "qny", "qnz", "qox", "qoy", "qoz", "qrough")
+PATH_FIELDS = PATH_X + PATH_NEXT + ("t_r", "t_g", "t_b", "le_r", "le_g", "le_b")
+
+
+class psf_path_out(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in PATH_FIELDS]
+
+
 # (name, restype, argtypes) of every exported function, in header order
 _vp, _u64, _u32, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
 _P = ctypes.POINTER
@@ -111,6 +140,8 @@ EXPORTS = [
     ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
     ("psf_estimate", ctypes.c_int, [_vp, _vp, _P(psf_estimate_args), _u64, ctypes.c_int32, ctypes.c_float,
                                     _vp, _vp, _vp]),
+    ("psf_sample_paths", ctypes.c_int, [_vp, _u32, _P(psf_camera), _P(psf_path_params), _P(psf_path_out), _vp]),
+    ("psf_philox", ctypes.c_int, [_vp, _vp, _u64, _vp, _vp]),
     ("psf_kernel_times", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     ("psf_kernel_name", ctypes.c_char_p, [_u32]),
     ("psf_last_error", ctypes.c_char_p, []),
@@ -428,3 +459,74 @@ class Batch:
 
 def version() -> str:
     return load().psf_version().decode()
+
+
+class Scene:
+    """Scene primitives for psf_sample_paths, copied once to device memory.
+    prims: dicts with kind ("quad" or "sphere"), p, u, v (quad half edges;
+    sphere: radius), albedo, emission, rough."""
+
+    def __init__(self, prims):
+        import torch
+        arr = (psf_prim * max(1, len(prims)))()
+        for i, q in enumerate(prims):
+            arr[i].kind = PSF_PRIM_SPHERE if q["kind"] == "sphere" else PSF_PRIM_QUAD
+            arr[i].p[:] = [float(c) for c in q["p"]]
+            if q["kind"] == "sphere":
+                arr[i].u[:] = [float(q["radius"]), 0.0, 0.0]
+            else:
+                arr[i].u[:] = [float(c) for c in q["u"]]
+                arr[i].v[:] = [float(c) for c in q["v"]]
+            arr[i].albedo[:] = [float(c) for c in q.get("albedo", (0.0, 0.0, 0.0))]
+            arr[i].emission[:] = [float(c) for c in q.get("emission", (0.0, 0.0, 0.0))]
+            arr[i].rough = float(q.get("rough", 1.0))
+        raw = bytes(arr)
+        self.n = len(prims)
+        self.dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+
+
+def camera(pos, fwd, up, fov_y_deg, width, height, spp=1):
+    c = psf_camera()
+    c.pos[:], c.fwd[:], c.up[:] = [float(v) for v in pos], [float(v) for v in fwd], [float(v) for v in up]
+    import math
+    c.fov_y = math.radians(float(fov_y_deg))
+    c.width, c.height, c.spp = int(width), int(height), int(spp)
+    return c
+
+
+def sample_paths(scene: Scene, cam, verts: int, mode: int = PSF_PATHS_LO, origin: int = PSF_ORIGIN_CAMERA,
+                 seed: int = 1, frame: int = 0, out: dict | None = None):
+    """psf_sample_paths: returns (x, next, t, le) -- the vertices as a record
+    dict (without values), their next vertices as a query dict, and the
+    throughput and emission triples, all device float32 arrays of
+    paths * verts entries (depth-major).  out: a dict of PATH_FIELDS arrays
+    to reuse."""
+    import torch
+    n = int(cam.width) * int(cam.height) * int(cam.spp) * int(verts)
+    if out is None:
+        out = {f: torch.empty(n, dtype=torch.float32, device="cuda") for f in PATH_FIELDS}
+    po = psf_path_out()
+    for f in PATH_FIELDS:
+        setattr(po, f, _ptr(_device_f32(out[f], f)))
+    prm = psf_path_params(int(verts), int(mode), int(origin), int(seed) & 0xFFFFFFFF, int(frame) & 0xFFFFFFFF)
+    _check(load().psf_sample_paths(ctypes.c_void_p(scene.dev.data_ptr()), scene.n, ctypes.byref(cam),
+                                   ctypes.byref(prm), ctypes.byref(po), current_stream()))
+    x = {k: out[k] for k in PATH_X}
+    nxt = {"px": out["qx"], "py": out["qy"], "pz": out["qz"], "nx": out["qnx"], "ny": out["qny"],
+           "nz": out["qnz"], "ox": out["qox"], "oy": out["qoy"], "oz": out["qoz"], "rough": out["qrough"]}
+    return x, nxt, (out["t_r"], out["t_g"], out["t_b"]), (out["le_r"], out["le_g"], out["le_b"])
+
+
+def philox(ctr, key):
+    """psf_philox on the device: ctr (n, 4) and key (n, 2) uint32 numpy
+    arrays; returns (n, 4) uint32."""
+    import numpy as np
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(ctr, dtype=np.uint32).view(np.int32)).cuda()
+    k = torch.from_numpy(np.ascontiguousarray(key, dtype=np.uint32).view(np.int32)).cuda()
+    n = int(c.shape[0])
+    o = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    _check(load().psf_philox(ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(k.data_ptr()), n,
+                             ctypes.c_void_p(o.data_ptr()), current_stream()))
+    return o.cpu().numpy().view(np.uint32)
+

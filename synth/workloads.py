@@ -258,3 +258,45 @@ def mis_weights(n: int, seed: int = 21, excluded: float = 0.1) -> np.ndarray:
     w = (p1 / (p1 + p2)).astype(np.float32)
     w[rng.random(n) < excluded] = 0.0
     return w
+
+
+# --------------------------------------------------------------------------
+# Scenes for the GPU path sampler (plain data: primitives and cameras).
+def furnace_scene(le=(1.0, 0.5, 0.25), albedo=(0.5, 0.6, 0.7)):
+    """The closed furnace: the unit sphere at the origin, emitting le and
+    reflecting diffusely with the given albedo; paths start at the centre."""
+    return [{"kind": "sphere", "p": (0.0, 0.0, 0.0), "radius": 1.0, "albedo": albedo, "emission": le,
+             "rough": 1.0}]
+
+
+def box_scene(light=(4.0, 4.0, 4.0), albedo=(0.6, 0.6, 0.6)):
+    """The tiny workload's open box [0, 1]^3 (floor, ceiling, back, left and
+    right unit quads; sphere of radius 0.3 at (0.5, 0.3, 0.5)) with a
+    0.5 x 0.5 emitter just below the ceiling; camera at (0.5, 0.5, -1.5)
+    looking along +z, vertical field of view 40 degrees."""
+    q = lambda p, u, v, a=albedo, r=1.0: {"kind": "quad", "p": p, "u": u, "v": v, "albedo": a, "rough": r}
+    prims = [
+        q((0.5, 0.0, 0.5), (0.5, 0.0, 0.0), (0.0, 0.0, 0.5)),         # floor
+        q((0.5, 1.0, 0.5), (0.5, 0.0, 0.0), (0.0, 0.0, 0.5)),         # ceiling
+        q((0.5, 0.5, 1.0), (0.5, 0.0, 0.0), (0.0, 0.5, 0.0)),         # back
+        q((0.0, 0.5, 0.5), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5), (0.6, 0.2, 0.2)),  # left
+        q((1.0, 0.5, 0.5), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5), (0.2, 0.6, 0.2), 0.2),  # right (glossy key)
+        {"kind": "sphere", "p": (0.5, 0.3, 0.5), "radius": 0.3, "albedo": (0.7, 0.7, 0.7), "rough": 1.0},
+        {"kind": "quad", "p": (0.5, 0.999, 0.5), "u": (0.25, 0.0, 0.0), "v": (0.0, 0.0, 0.25),
+         "albedo": (0.0, 0.0, 0.0), "emission": light, "rough": 1.0},
+    ]
+    cam = {"pos": (0.5, 0.5, -1.5), "fwd": (0.0, 0.0, 1.0), "up": (0.0, 1.0, 0.0), "fov_y_deg": 40.0}
+    return prims, cam
+
+
+def square_light_scene(h=1.0, s=0.5, light=(3.0, 2.0, 1.0), albedo=(0.8, 0.5, 0.3)):
+    """A large diffuse floor (y = 0) under a square emitter of half size s at
+    height h centred above the origin; the camera looks straight down at the
+    origin from half the height with a narrow field of view, so every first
+    vertex is (all but) the floor point below the emitter's centre."""
+    prims = [{"kind": "quad", "p": (0.0, 0.0, 0.0), "u": (50.0, 0.0, 0.0), "v": (0.0, 0.0, 50.0),
+              "albedo": albedo, "rough": 1.0},
+             {"kind": "quad", "p": (0.0, h, 0.0), "u": (s, 0.0, 0.0), "v": (0.0, 0.0, s),
+              "albedo": (0.0, 0.0, 0.0), "emission": light, "rough": 1.0}]
+    cam = {"pos": (0.0, 0.5 * h, 0.0), "fwd": (0.0, -1.0, 0.0), "up": (0.0, 0.0, 1.0), "fov_y_deg": 0.01}
+    return prims, cam

@@ -60,7 +60,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"psf_config": psf.psf_config, "psf_records": psf.psf_records,
                "psf_queries": psf.psf_queries, "psf_stats": psf.psf_stats,
                "psf_session": psf.psf_session, "psf_estimate_args": psf.psf_estimate_args,
-               "psf_step_args": psf.psf_step_args}
+               "psf_step_args": psf.psf_step_args, "psf_prim": psf.psf_prim, "psf_camera": psf.psf_camera,
+               "psf_path_params": psf.psf_path_params, "psf_path_out": psf.psf_path_out}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psf.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
