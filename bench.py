@@ -359,7 +359,7 @@ def form_progressive(torch, psf, W, iters=16, width=1280, height=720, verts=4):
     scene = psf.Scene(prims)
     cam = psf.camera((0.5, 0.5, 0.02), (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), 60.0, width, height, 1)
     n = width * height * verts
-    cfg = dict(W.tiny()["table"], log2_slots=22, flags=psf.PSF_FLAG_TIMING, cam=(0.5, 0.5, 0.02),
+    cfg = dict(W.tiny()["table"], log2_slots=23, flags=psf.PSF_FLAG_TIMING, cam=(0.5, 0.5, 0.02),
                kappa=W.kappa_for(60.0, height, 4.0, -10), e_min=-10)
     t = psf.Table(**dict(cfg, max_batch=n))
     samples = torch.empty((3, n), dtype=torch.float32, device="cuda")
