@@ -10,7 +10,8 @@ function, with optional per-record MIS weights: Sec. 2.5), Sec. 2.4 Eq. 10-11
 (temporal blend, counter reset), Sec. 2.6 (spatio-directional hashing; the key specification is this project's, written
 out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state),
 and, for the two-field estimators, Sec. 2.5, Sec. 4.2 (Eq. 25) and Sec. 5
-(Eq. 28) in ``estimate`` below (plain numpy in binary64 over the lookups).
+(Eq. 28) in ``estimate`` below (plain numpy in binary64 over the lookups);
+``ShOracle`` holds the two-band SH YCoCg cell payload of Sec. 2.6.
 """
 from __future__ import annotations
 
@@ -79,6 +80,17 @@ def _load():
     lib.orc_sharded_export.restype = u64
     lib.orc_sharded_export.argtypes = [vp, vp, vp, vp, vp, vp, u64]
     lib.orc_sharded_counters.argtypes = [vp, vp, vp, vp]
+    lib.orc_sh_create.restype = vp
+    lib.orc_sh_create.argtypes = lib.orc_create.argtypes
+    lib.orc_sh_destroy.argtypes = [vp]
+    lib.orc_sh_insert.argtypes = [vp, ctypes.POINTER(_Records), u64]
+    lib.orc_sh_update.restype = u64
+    lib.orc_sh_update.argtypes = [vp]
+    lib.orc_sh_query.argtypes = [vp, ctypes.POINTER(_Records), u64, vp, vp]
+    lib.orc_sh_count.restype = u64
+    lib.orc_sh_count.argtypes = [vp]
+    lib.orc_sh_export.restype = u64
+    lib.orc_sh_export.argtypes = [vp, vp, vp, vp, u64]
     _lib = lib
     return lib
 
@@ -292,6 +304,59 @@ class ShardedOracle(Oracle):
 
     def reset_region(self, lo, hi):
         raise NotImplementedError("the sharded oracle has no reset")
+
+
+class ShOracle:
+    """A table whose cells hold the two-band SH luminance and the YCoCg
+    chroma (Sec. 2.6; the reading is written out in psf_oracle.cpp): per
+    frame a ridge least-squares fit of the four luminance coefficients over
+    the samples' normals and the chroma means, blended by Eq. 10-11; a
+    lookup evaluates the luminance at the query's normal.  Binary64."""
+
+    def __init__(self, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0, max_level=15, normal_bins_log2=0,
+                 dir_bins_log2=3, rough_thr=0.3, alpha_mode=ALPHA_PAPER, alpha=0.2, t_max=5.0, **_ignored):
+        self._lib = _load()
+        cam_arr = (ctypes.c_float * 3)(*[float(c) for c in cam])
+        self._h = self._lib.orc_sh_create(cam_arr, float(np.float32(kappa)), int(e_min), int(max_level),
+                                          int(normal_bins_log2), int(dir_bins_log2), float(np.float32(rough_thr)),
+                                          int(alpha_mode), float(np.float32(alpha)), float(np.float32(t_max)))
+
+    def close(self):
+        if self._h:
+            self._lib.orc_sh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, rec):
+        n = Oracle._n(rec)
+        p = _Pack(rec, n)
+        self._lib.orc_sh_insert(self._h, ctypes.byref(p.s), n)
+
+    def update(self) -> int:
+        return int(self._lib.orc_sh_update(self._h))
+
+    def query(self, rec):
+        n = Oracle._n(rec)
+        p = _Pack(rec, n)
+        out = np.zeros((3, n), dtype=np.float64)
+        found = np.zeros(n, dtype=np.uint8)
+        self._lib.orc_sh_query(self._h, ctypes.byref(p.s), n, out.ctypes.data, found.ctypes.data)
+        return out, found
+
+    def export(self):
+        cap = int(self._lib.orc_sh_count(self._h))
+        keys = np.zeros(cap, dtype=np.uint64)
+        c_old = np.zeros(cap, dtype=np.float64)
+        coeff = np.zeros((6, cap), dtype=np.float64)
+        if cap:
+            got = self._lib.orc_sh_export(self._h, keys.ctypes.data, c_old.ctypes.data, coeff.ctypes.data, cap)
+            assert got == cap
+        return {"keys": keys, "c_old": c_old, "coeff": coeff}
 
 
 # --------------------------------------------------------------------------

@@ -625,3 +625,184 @@ void orc_sharded_counters(void* h, uint64_t* skipped, uint64_t* coord_overflow, 
 }
 
 }  // extern "C"
+
+// --------------------------------------------------------------------------
+// Two-band spherical-harmonic luminance payload in YCoCg (Sec. 2.6: within a
+// cell the luminance varies with the normal as two SH bands; chroma is one
+// value per cell).  The paper gives no projection; this project's reading:
+// each frame fits the four band-0/1 coefficients of the luminance to the
+// cell's samples by weighted least squares over their normals, with a ridge
+// of 1e-7 * (sum of weights) on the band-1 coefficients only (so the system
+// is always positive definite, a constant field is reproduced exactly and a
+// cell whose normals are all equal reproduces its mean there); the chroma
+// pair is the frame's weighted mean.  The six numbers are blended like the
+// approximant (Eq. 10-11 with the cell's counters).  A lookup evaluates the
+// luminance at the query's normal and converts YCoCg back to RGB.
+
+struct ShCell {
+  double n_new = 0.0, g[10] = {}, r[4] = {}, co = 0.0, cg = 0.0;  // frame sums
+  double c_old = 0.0, c[4] = {}, co_m = 0.0, cg_m = 0.0;          // state
+};
+
+struct ShOracle {
+  Config cfg;
+  std::map<uint64_t, ShCell> cells;
+  uint64_t skipped = 0;
+};
+
+// Real SH basis of bands 0 and 1: 1 / (2 sqrt(pi)) and sqrt(3 / (4 pi)) (y, z, x).
+static void sh_basis(double x, double y, double z, double b[4]) {
+  const double k0 = 0.28209479177387814, k1 = 0.4886025119029199;
+  b[0] = k0;
+  b[1] = k1 * y;
+  b[2] = k1 * z;
+  b[3] = k1 * x;
+}
+
+// index of the upper-triangle entry (i <= j) of a symmetric 4 x 4 matrix
+static int tri(int i, int j) {
+  static const int idx[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+  return idx[i][j];
+}
+
+// (G + lambda D) c = r by Cholesky, D = diag(0, 1, 1, 1).
+static void sh_solve(const double g[10], const double r[4], double lambda, double c[4]) {
+  double a[4][4], l[4][4] = {};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) a[i][j] = g[tri(i, j)] + ((i == j && i > 0) ? lambda : 0.0);
+  for (int j = 0; j < 4; ++j) {
+    double d = a[j][j];
+    for (int k = 0; k < j; ++k) d -= l[j][k] * l[j][k];
+    l[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < 4; ++i) {
+      double v = a[i][j];
+      for (int k = 0; k < j; ++k) v -= l[i][k] * l[j][k];
+      l[i][j] = v / l[j][j];
+    }
+  }
+  double y[4];
+  for (int i = 0; i < 4; ++i) {
+    double v = r[i];
+    for (int k = 0; k < i; ++k) v -= l[i][k] * y[k];
+    y[i] = v / l[i][i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 4; ++k) v -= l[k][i] * c[k];
+    c[i] = v / l[i][i];
+  }
+}
+
+extern "C" {
+
+void* orc_sh_create(const float* cam, float kappa, int e_min, int max_level, int normal_bins_log2,
+                    int dir_bins_log2, float rough_thr, int alpha_mode, float alpha, float t_max) {
+  ShOracle* o = new ShOracle();
+  Oracle* tmp = static_cast<Oracle*>(orc_create(cam, kappa, e_min, max_level, normal_bins_log2, dir_bins_log2,
+                                                rough_thr, alpha_mode, alpha, t_max));
+  o->cfg = tmp->cfg;
+  delete tmp;
+  return o;
+}
+
+void orc_sh_destroy(void* h) { delete static_cast<ShOracle*>(h); }
+
+// Per cell and frame: the weights, the Gram matrix of the basis over the
+// samples' normals, the basis-weighted luminance and the chroma sums.
+void orc_sh_insert(void* h, const orc_records* r, uint64_t n) {
+  ShOracle* o = static_cast<ShOracle*>(h);
+  const float* const* f = r->f;
+  for (uint64_t i = 0; i < n; ++i) {
+    const float R = f[9][i], G = f[10][i], B = f[11][i];
+    const float w = f[14] ? f[14][i] : 1.0f;
+    KeyResult k = key_at(o->cfg, r, i);
+    if (!k.valid || !finite3(R, G, B) || !(std::isfinite(w) && w > 0.0f)) {
+      o->skipped++;
+      continue;
+    }
+    ShCell& c = o->cells[k.key];
+    const double wd = w;
+    const double y = 0.25 * R + 0.5 * G + 0.25 * B;
+    const double co = 0.5 * R - 0.5 * B;
+    const double cg = -0.25 * R + 0.5 * G - 0.25 * B;
+    double b[4];
+    sh_basis(f[3][i], f[4][i], f[5][i], b);
+    c.n_new += wd;
+    for (int a = 0; a < 4; ++a) {
+      for (int e = a; e < 4; ++e) c.g[tri(a, e)] += wd * b[a] * b[e];
+      c.r[a] += wd * y * b[a];
+    }
+    c.co += wd * co;
+    c.cg += wd * cg;
+  }
+}
+
+uint64_t orc_sh_update(void* h) {
+  ShOracle* o = static_cast<ShOracle*>(h);
+  uint64_t touched = 0;
+  for (auto& kv : o->cells) {
+    ShCell& c = kv.second;
+    if (c.n_new == 0.0) continue;
+    double fit[4];
+    sh_solve(c.g, c.r, 1e-7 * c.n_new, fit);
+    const double a = alpha_of(o->cfg, c.n_new, c.c_old);
+    for (int k = 0; k < 4; ++k) c.c[k] = (1.0 - a) * c.c[k] + a * fit[k];
+    c.co_m = (1.0 - a) * c.co_m + a * (c.co / c.n_new);
+    c.cg_m = (1.0 - a) * c.cg_m + a * (c.cg / c.n_new);
+    c.c_old += c.n_new;
+    c.n_new = 0.0;
+    for (double& v : c.g) v = 0.0;
+    for (double& v : c.r) v = 0.0;
+    c.co = c.cg = 0.0;
+    touched++;
+  }
+  return touched;
+}
+
+void orc_sh_query(void* h, const orc_records* r, uint64_t n, double* out_rgb, uint8_t* found) {
+  ShOracle* o = static_cast<ShOracle*>(h);
+  const float* const* f = r->f;
+  for (uint64_t i = 0; i < n; ++i) {
+    KeyResult k = key_at(o->cfg, r, i);
+    double v[3] = {0.0, 0.0, 0.0};
+    uint8_t hit = 0;
+    if (k.valid) {
+      auto it = o->cells.find(k.key);
+      if (it != o->cells.end() && it->second.c_old > 0.0) {
+        const ShCell& c = it->second;
+        double b[4];
+        sh_basis(f[3][i], f[4][i], f[5][i], b);
+        const double y = c.c[0] * b[0] + c.c[1] * b[1] + c.c[2] * b[2] + c.c[3] * b[3];
+        v[0] = y + c.co_m - c.cg_m;
+        v[1] = y + c.cg_m;
+        v[2] = y - c.co_m - c.cg_m;
+        hit = 1;
+      }
+    }
+    out_rgb[i] = v[0];
+    out_rgb[n + i] = v[1];
+    out_rgb[2 * n + i] = v[2];
+    if (found) found[i] = hit;
+  }
+}
+
+uint64_t orc_sh_count(void* h) { return static_cast<ShOracle*>(h)->cells.size(); }
+
+// Cells in ascending key order: keys, c_old, and the six state numbers as
+// 6 x cap (SoA: c0..c3, Co, Cg).
+uint64_t orc_sh_export(void* h, uint64_t* keys, double* c_old, double* coeff, uint64_t cap) {
+  ShOracle* o = static_cast<ShOracle*>(h);
+  uint64_t i = 0;
+  for (auto& kv : o->cells) {
+    if (i >= cap) break;
+    keys[i] = kv.first;
+    c_old[i] = kv.second.c_old;
+    for (int k = 0; k < 4; ++k) coeff[k * cap + i] = kv.second.c[k];
+    coeff[4 * cap + i] = kv.second.co_m;
+    coeff[5 * cap + i] = kv.second.cg_m;
+    ++i;
+  }
+  return i;
+}
+
+}  // extern "C"
