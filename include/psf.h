@@ -171,7 +171,29 @@ typedef struct psf_config {
                                 weights that fell on it and its sample mean
                                 the weighted mean; Eq. 11 takes the weighted
                                 counters. */
+  uint32_t payload;          /* PSF_PAYLOAD_RGB: the approximant is an RGB
+                                triple per cell.  PSF_PAYLOAD_SH2_YCOCG:
+                                luminance as two spherical-harmonic bands
+                                over the normal plus YCoCg chroma (below);
+                                F32 state and the direct insert strategy
+                                only (NOT_SUPPORTED otherwise). */
 } psf_config;
+
+/* Cell payloads.  SH2_YCOCG (Sec. 2.6: normal variation within a cell as
+ * two SH bands of luminance in a YCoCg colour decomposition), this
+ * library's reading of the unspecified projection: each frame fits, per
+ * cell, the four band-0/1 luminance coefficients (real SH, basis
+ * 1/(2 sqrt(pi)) and sqrt(3/(4 pi)) (n_y, n_z, n_x)) to the samples by
+ * weighted least squares over their normals, in binary64, with a ridge of
+ * 1e-7 times the cell's weight on the band-1 coefficients (the system is
+ * always definite; a constant field is reproduced exactly; a cell whose
+ * normals are all equal reproduces its mean at that normal), and takes the
+ * weighted mean of the chroma pair (Co, Cg); these six numbers are the
+ * cell's state (24 bytes), blended by Eq. 10-11 with the cell's counters.
+ * A lookup evaluates the luminance at the query's normal and returns RGB
+ * (R = Y + Co - Cg, G = Y + Cg, B = Y - Co - Cg).  Key the cells with
+ * normal_bins_log2 = 0 to let the payload, not the key, carry the normal. */
+enum { PSF_PAYLOAD_RGB = 0, PSF_PAYLOAD_SH2_YCOCG = 1 };
 
 /* Vertex records, structure of arrays, N float32 each (device memory).
  * ox..oz is the outgoing direction omega_o (pointing back along the path,
@@ -345,6 +367,14 @@ psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint3
  * serialises them.  Synchronises stream. */
 psf_status psf_export_cells_noalloc(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
                                     float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
+
+/* Export of an SH2_YCOCG table: keys, c_old and the six state numbers per
+ * occupied cell into host arrays of capacity cap (coeff: 6 * cap floats,
+ * SoA: the four luminance coefficients, then Co, then Cg).  Pending frame
+ * sums are not exported.  Otherwise as psf_export_cells (NOT_SUPPORTED for
+ * an RGB table).  Synchronises stream. */
+psf_status psf_export_sh_cells(psf_table* t, uint64_t* keys, uint32_t* c_old, float* coeff, uint64_t cap,
+                               uint64_t* count, psf_stream stream);
 
 /* Batched form: one iteration (insert, temporal update, query) of k
  * independent sessions, each with its own table, in three launches that

@@ -148,11 +148,13 @@ bool validate(const psf_config* c, std::string* why) {
     return bad("unknown flags");
   if (c->max_batch > (1ull << 31)) return bad("max_batch must be <= 2^31");
   if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
+  if (c->payload > PSF_PAYLOAD_SH2_YCOCG) return bad("payload must be RGB or SH2_YCOCG");
   if (c->weighted > 1) return bad("weighted must be 0 or 1");
   return true;
 }
 
 struct Layout {
+  size_t sh = 0, sh_acc = 0;
   size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_v = 0, runs = 0,
          runs_t = 0, perm = 0, total = 0;
   uint32_t part_log2 = 0;
@@ -171,7 +173,7 @@ Layout layout_of(const psf_config& c) {
   L.part_log2 = c.part_log2 ? c.part_log2 : def;
   if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;
   const uint64_t P = 1ull << (c.log2_slots - L.part_log2);
-  L.part = c.insert_mode != PSF_INSERT_DIRECT && P <= kMaxPartitions;
+  L.part = c.insert_mode != PSF_INSERT_DIRECT && P <= kMaxPartitions && c.payload == PSF_PAYLOAD_RGB;
   size_t off = 0;
   L.stats = off;
   off = align_up(off + sizeof(psf::DevStats), 256);
@@ -183,6 +185,12 @@ Layout layout_of(const psf_config& c) {
   off = align_up(off + S * 8, 256);
   L.acc = off;
   off = align_up(off + S * sizeof(psf::Acc), 256);
+  if (c.payload == PSF_PAYLOAD_SH2_YCOCG) {
+    L.sh = off;
+    off = align_up(off + S * sizeof(psf::ShState), 256);
+    L.sh_acc = off;
+    off = align_up(off + S * sizeof(psf::ShAcc), 256);
+  }
   if (L.part) {
     const uint64_t tile = psf::bin_tile(c.bin_per ? c.bin_per : kDefaultBinPer);
     L.cap = c.max_batch ? c.max_batch : kDefaultBatch;
@@ -255,7 +263,10 @@ bool transpose_runs(const psf_table* t, uint32_t ntiles) {
 
 psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream_t s) {
   hipError_t e;
-  if (t->partitioned) {
+  if (t->tv.sh) {
+    e = timed(t, PSF_K_INSERT_DIRECT, s, [&] { return psf::launch_insert_sh(rp, n, t->kp, t->tv, s); });
+    if (e != hipSuccess) return hip_fail(e, "insert launch");
+  } else if (t->partitioned) {
     for (uint64_t off = 0; off < n; off += t->pv.capacity) {
       const uint64_t m = (n - off < t->pv.capacity) ? n - off : t->pv.capacity;
       const psf::RecPtrs sub = offset_rec(rp, off);
@@ -282,7 +293,10 @@ psf_status do_insert(psf_table* t, const psf::RecPtrs& rp, uint64_t n, hipStream
 }
 
 psf_status do_update(psf_table* t, hipStream_t s) {
-  hipError_t e = timed(t, PSF_K_UPDATE, s, [&] { return psf::launch_update(t->tv, t->bp, nslots(t), s); });
+  hipError_t e = timed(t, PSF_K_UPDATE, s, [&] {
+    return t->tv.sh ? psf::launch_update_sh(t->tv, t->bp, nslots(t), s)
+                    : psf::launch_update(t->tv, t->bp, nslots(t), s);
+  });
   if (e != hipSuccess) return hip_fail(e, "update launch");
   t->pending = false;
   t->updates++;
@@ -299,7 +313,8 @@ bool same_vertices(const psf_records* r, const psf_queries* q) {
 psf_status do_query(psf_table* t, const psf::QryPtrs& q, uint64_t n, float* out, uint8_t* found,
                     hipStream_t s) {
   hipError_t e = timed(t, PSF_K_QUERY, s, [&] {
-    return psf::launch_query(q, n, t->kp, t->tv, t->cfg.state_dtype, out, found, s);
+    return t->tv.sh ? psf::launch_query_sh(q, n, t->kp, t->tv, out, found, s)
+                    : psf::launch_query(q, n, t->kp, t->tv, t->cfg.state_dtype, out, found, s);
   });
   return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
 }
@@ -321,6 +336,9 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if (!out) return fail(PSF_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   if (!validate(cfg, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (cfg->payload == PSF_PAYLOAD_SH2_YCOCG &&
+      (cfg->state_dtype != PSF_STATE_F32 || cfg->insert_mode == PSF_INSERT_PARTITIONED))
+    return fail(PSF_NOT_SUPPORTED, "the SH payload takes F32 state and the direct insert strategy");
   const Layout L = layout_of(*cfg);
   if (device_buffer) {
     if (buffer_bytes < L.total)
@@ -349,6 +367,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   t->tv.slots = reinterpret_cast<psf::Slot*>(b + L.slots);
   t->tv.keys = reinterpret_cast<unsigned long long*>(b + L.keys);
   t->tv.acc = reinterpret_cast<psf::Acc*>(b + L.acc);
+  t->tv.sh = L.sh ? reinterpret_cast<psf::ShState*>(b + L.sh) : nullptr;
+  t->tv.sh_acc = L.sh_acc ? reinterpret_cast<psf::ShAcc*>(b + L.sh_acc) : nullptr;
   t->tv.log2_slots = cfg->log2_slots;
   t->tv.part_log2 = L.part_log2;
   t->tv.max_probe = cfg->max_probe < (1u << L.part_log2) ? cfg->max_probe : (1u << L.part_log2);
@@ -377,6 +397,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   }
   if (e == hipSuccess) e = psf::launch_zero(t->tv.stats, L.slots - L.stats, s);
   if (e == hipSuccess) e = psf::launch_clear(t->tv, nslots(t), s);
+  if (e == hipSuccess && t->tv.sh) e = psf::launch_clear_sh(t->tv, nslots(t), s);
   if (e != hipSuccess) {
     if (t->timer) {
       t->timer->destroy();
@@ -489,6 +510,7 @@ PSF_API psf_status psf_reset(psf_table* t, uint32_t what, psf_stream stream) {
   hipError_t e = hipSuccess;
   if (what & PSF_RESET_CLEAR) {
     e = psf::launch_clear(t->tv, nslots(t), s);
+    if (e == hipSuccess && t->tv.sh) e = psf::launch_clear_sh(t->tv, nslots(t), s);
     t->pending = false;
   } else if (what & PSF_RESET_COUNTERS) {
     e = psf::launch_reset_counters(t->tv, nslots(t), s);
@@ -510,6 +532,7 @@ PSF_API psf_status psf_query_levels(psf_table* t, const psf_queries* q, uint64_t
   if (!qry_ok(q, &why)) return fail(PSF_INVALID_ARGUMENT, why);
   if (!d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
   if (levels_up > 15) return fail(PSF_INVALID_ARGUMENT, "levels_up must be <= 15");
+  if (t->tv.sh) return fail(PSF_NOT_SUPPORTED, "multi-level lookup of an SH payload table");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   hipError_t e = timed(t, PSF_K_QUERY, s, [&] {
@@ -536,6 +559,7 @@ PSF_API psf_status psf_progressive_step(psf_table* t, const psf_records* x, cons
   if ((a->le_r != nullptr) != (a->le_g != nullptr) || (a->le_r != nullptr) != (a->le_b != nullptr))
     return fail(PSF_INVALID_ARGUMENT, "emission arrays: all three or none");
   if (!d_samples) return fail(PSF_INVALID_ARGUMENT, "sample array is NULL");
+  if (t->tv.sh) return fail(PSF_NOT_SUPPORTED, "progressive step on an SH payload table");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   psf::StepPtrs sp{qry_ptrs(next), a->le_r, a->le_g, a->le_b, a->t_r, a->t_g, a->t_b};
@@ -632,6 +656,7 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
                                     float* state_rgb, uint64_t cap, uint64_t* count,
                                     psf_stream stream) {
   if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  if (t->tv.sh) return fail(PSF_NOT_SUPPORTED, "an SH payload table exports with psf_export_sh_cells");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   uint64_t occ = 0;
@@ -659,6 +684,39 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
   if (e == hipSuccess && state_rgb) {
     for (int ch = 0; ch < 3 && e == hipSuccess; ++ch)
       e = hipMemcpyAsync(state_rgb + ch * cap, drgb + ch * occ, occ * 4, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
+}
+
+PSF_API psf_status psf_export_sh_cells(psf_table* t, uint64_t* keys, uint32_t* c_old, float* coeff, uint64_t cap,
+                                       uint64_t* count, psf_stream stream) {
+  if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  if (!t->tv.sh) return fail(PSF_NOT_SUPPORTED, "not an SH payload table");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  uint64_t occ = 0;
+  psf_status st = count_occupied(t, s, &occ);
+  if (st != PSF_OK) return st;
+  *count = occ;
+  if (occ > cap) return fail(PSF_BUFFER_TOO_SMALL, "more occupied cells than cap");
+  if (occ == 0) return PSF_OK;
+  const size_t bytes = 256 + occ * 8 + occ * 4 + occ * 24;
+  char* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc export scratch");
+  auto* cur = reinterpret_cast<unsigned long long*>(d);
+  auto* dk = reinterpret_cast<unsigned long long*>(d + 256);
+  auto* dc = reinterpret_cast<uint32_t*>(d + 256 + occ * 8);
+  auto* dv = reinterpret_cast<float*>(dc + occ);
+  e = psf::launch_zero(cur, 16, s);
+  if (e == hipSuccess) e = psf::launch_compact_sh(t->tv, nslots(t), cur, occ, dk, dc, dv, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(keys, dk, occ * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && c_old) e = hipMemcpyAsync(c_old, dc, occ * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && coeff) {
+    for (int k = 0; k < 6 && e == hipSuccess; ++k)
+      e = hipMemcpyAsync(coeff + k * cap, dv + k * occ, occ * 4, hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d);
@@ -704,6 +762,7 @@ PSF_API psf_status psf_export_cells_noalloc(psf_table* t, uint64_t* keys, uint32
                                             float* state_rgb, uint64_t cap, uint64_t* count,
                                             psf_stream stream) {
   if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  if (t->tv.sh) return fail(PSF_NOT_SUPPORTED, "an SH payload table exports with psf_export_sh_cells");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   char* d = nullptr;
@@ -917,6 +976,7 @@ PSF_API psf_status psf_estimate(psf_table* t_oe, psf_table* t_fli, const psf_est
   if (!a->gr || !a->gg || !a->gb || !a->wp) return fail(PSF_INVALID_ARGUMENT, "sample and weight arrays are required");
   if (mode != PSF_EST_CV && mode != PSF_EST_BIASED) return fail(PSF_INVALID_ARGUMENT, "mode must be CV or BIASED");
   if (!std::isfinite(param)) return fail(PSF_INVALID_ARGUMENT, "param must be finite");
+  if (t_oe->tv.sh || t_fli->tv.sh) return fail(PSF_NOT_SUPPORTED, "estimators on SH payload tables");
   if (!d_out_rgb) return fail(PSF_INVALID_ARGUMENT, "output array is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t_oe->last = s;

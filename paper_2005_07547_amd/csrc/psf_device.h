@@ -71,11 +71,30 @@ struct alignas(16) BlockTouch {
 };
 constexpr uint32_t kTouchEntries = 8192;
 
+// Two-band SH payload (Sec. 2.6): a cell's state, the four luminance
+// coefficients and the chroma pair (24 bytes, padded to 32), and its frame
+// sums in binary64: weight, Gram matrix of the basis over the sample
+// normals (upper triangle), basis-weighted luminance, chroma sums.
+struct alignas(16) ShState {
+  float c[4];
+  float co, cg;
+  float pad[2];
+};
+struct alignas(16) ShAcc {
+  double n;
+  double g[10];
+  double r[4];
+  double co, cg;
+  double pad;
+};
+
 // View of one table handed to kernels by value.
 struct TableView {
   Slot* slots;
   unsigned long long* keys;  // mirror of slots[].key, read by the partitioned merge
   Acc* acc;
+  ShState* sh;               // SH payload only (else null)
+  ShAcc* sh_acc;
   DevStats* stats;
   BlockTouch* touch;         // kTouchEntries
   uint32_t log2_slots;

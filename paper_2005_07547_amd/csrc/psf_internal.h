@@ -150,6 +150,17 @@ hipError_t launch_sample_paths(const PathPrim* prims, uint32_t np, const PathCam
                                uint64_t n_paths, const PathOut& out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out, hipStream_t s);
 
+// SH payload tables (Sec. 2.6): direct insert into binary64 frame sums,
+// streaming fit + blend, lookup evaluating the luminance at the normal.
+hipError_t launch_insert_sh(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
+                            hipStream_t s);
+hipError_t launch_update_sh(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s);
+hipError_t launch_query_sh(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv, float* out,
+                           uint8_t* found, hipStream_t s);
+hipError_t launch_compact_sh(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                             unsigned long long* keys, uint32_t* c_old, float* coeff, hipStream_t s);
+hipError_t launch_clear_sh(const TableView& tv, uint64_t nslots, hipStream_t s);
+
 hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           unsigned long long* cursor, uint64_t cap, unsigned long long* keys,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s);

@@ -418,6 +418,205 @@ __global__ void k_compact(TableView tv, uint64_t nslots, int32_t dtype, unsigned
   }
 }
 
+// ------------------------------------------------------------------ SH payload (Sec. 2.6)
+// Luminance as two real SH bands over the normal, chroma (Co, Cg) as means;
+// per frame a ridge least-squares fit in binary64 (the reading is stated in
+// psf.h at PSF_PAYLOAD_SH2_YCOCG).
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double b[4]) {
+  const double k0 = 0.28209479177387814, k1 = 0.4886025119029199;
+  b[0] = k0;
+  b[1] = k1 * y;
+  b[2] = k1 * z;
+  b[3] = k1 * x;
+}
+
+// upper-triangle index of entry (i, j) of a symmetric 4 x 4 matrix
+__device__ __forceinline__ int sh_tri(int i, int j) {
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  return lo == 0 ? hi : (lo == 1 ? 3 + hi : (lo == 2 ? 5 + hi : 9));
+}
+
+// (G + lambda diag(0, 1, 1, 1)) c = r, Cholesky in binary64
+__device__ __forceinline__ void sh_solve(const double g[10], const double r[4], double lambda, double c[4]) {
+  double a[4][4], l[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[i][j] = g[sh_tri(i, j)] + ((i == j && i > 0) ? lambda : 0.0);
+      l[i][j] = 0.0;
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double d = a[j][j];
+    for (int k = 0; k < j; ++k) d -= l[j][k] * l[j][k];
+    l[j][j] = sqrt(d);
+    for (int i = j + 1; i < 4; ++i) {
+      double v = a[i][j];
+      for (int k = 0; k < j; ++k) v -= l[i][k] * l[j][k];
+      l[i][j] = v / l[j][j];
+    }
+  }
+  double y[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = r[i];
+    for (int k = 0; k < i; ++k) v -= l[i][k] * y[k];
+    y[i] = v / l[i][i];
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 4; ++k) v -= l[k][i] * c[k];
+    c[i] = v / l[i][i];
+  }
+}
+
+// One record per thread: key, find or claim the slot, binary64 atomics on
+// the cell's frame sums (weight, Gram matrix, basis-weighted luminance,
+// chroma).
+__global__ void __launch_bounds__(256) k_insert_sh(RecPtrs rec, uint64_t n, KeyParams kp, TableView tv) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = false, ovf = false;
+  uint64_t key = kEmpty;
+  float r = 0.0f, g = 0.0f, b = 0.0f, w = 1.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
+  if (i < n) {
+    const bool hr = rec.rough != nullptr;
+    const float ro = hr ? rec.rough[i] : 0.0f;
+    const bool gl = hr && ro < kp.rough_thr;
+    const bool hf = rec.footprint != nullptr;
+    nx = rec.nx[i];
+    ny = rec.ny[i];
+    nz = rec.nz[i];
+    r = rec.r[i];
+    g = rec.g[i];
+    b = rec.b[i];
+    valid = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], nx, ny, nz, gl ? rec.ox[i] : 0.0f,
+                     gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro, hf, hf ? rec.footprint[i] : 0.0f, key,
+                     ovf);
+    valid = valid && finite3(r, g, b);
+    if (rec.weight) {
+      w = rec.weight[i];
+      valid = valid && __builtin_isfinite(w) && w > 0.0f;
+    }
+  }
+  wave_count(stat_lane(tv.stats->skipped, blockIdx.x), i < n && !valid);
+  wave_count(stat_lane(tv.stats->coord_overflow, blockIdx.x), valid && ovf);
+  if (!valid) return;
+  uint32_t probes;
+  const uint64_t slot = find_or_claim(tv, key, &probes);
+  if (slot == ~0ull) {
+    atomicAdd(&tv.stats->dropped, 1ull);
+    return;
+  }
+  ShAcc* a = &tv.sh_acc[slot];
+  const double wd = w;
+  const double y = 0.25 * (double)r + 0.5 * (double)g + 0.25 * (double)b;
+  const double co = 0.5 * (double)r - 0.5 * (double)b;
+  const double cg = -0.25 * (double)r + 0.5 * (double)g - 0.25 * (double)b;
+  double bs[4];
+  sh_basis(nx, ny, nz, bs);
+  atomicAdd(&a->n, wd);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+#pragma unroll
+    for (int q = p; q < 4; ++q) atomicAdd(&a->g[sh_tri(p, q)], wd * bs[p] * bs[q]);
+    atomicAdd(&a->r[p], wd * y * bs[p]);
+  }
+  atomicAdd(&a->co, wd * co);
+  atomicAdd(&a->cg, wd * cg);
+}
+
+// Streaming pass: every cell with frame sums gets its fit blended in
+// (Eq. 10-11 on the counters, FP32 blend of the six numbers) and its sums
+// cleared; per-block touch counts as in the RGB update.
+__global__ void __launch_bounds__(256) k_update_sh(TableView tv, BlendParams bp, uint64_t nslots) {
+  __shared__ uint32_t s_touched;
+  if (threadIdx.x == 0) s_touched = 0;
+  __syncthreads();
+  const bool wtd = weighted(tv);
+  uint32_t touched = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    ShAcc a = tv.sh_acc[s];
+    if (a.n == 0.0) continue;
+    double fit[4];
+    sh_solve(a.g, a.r, 1e-7 * a.n, fit);
+    const uint32_t c_old = tv.slots[s].c_old;
+    const uint32_t nw = wtd ? __float_as_uint((float)a.n) : (uint32_t)a.n;
+    const float alpha = blend_alpha(bp, nw, c_old, wtd);
+    ShState st = tv.sh[s];
+    const float v[6] = {(float)fit[0], (float)fit[1], (float)fit[2], (float)fit[3], (float)(a.co / a.n),
+                        (float)(a.cg / a.n)};
+    float* sv[6] = {&st.c[0], &st.c[1], &st.c[2], &st.c[3], &st.co, &st.cg};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) *sv[k] = alpha == 1.0f ? v[k] : (1.0f - alpha) * *sv[k] + alpha * v[k];
+    tv.sh[s] = st;
+    tv.slots[s].c_old = counter_add(c_old, nw, wtd);
+    tv.sh_acc[s] = ShAcc{};
+    ++touched;
+  }
+  for (int off = 32; off > 0; off >>= 1) touched += __shfl_xor(touched, off);
+  if (lane_id() == 0 && touched) atomicAdd(&s_touched, touched);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BlockTouch* bt = &tv.touch[blockIdx.x];
+    bt->last = s_touched;
+    bt->total += s_touched;
+  }
+}
+
+// Lookup: the luminance at the query's normal and the chroma, as RGB.
+__global__ void __launch_bounds__(256) k_query_sh(QryPtrs q, uint64_t n, KeyParams kp, TableView tv, float* out,
+                                                  uint8_t* found) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = query_key(kp, q, i);
+  float rgb[3] = {0.0f, 0.0f, 0.0f};
+  uint8_t hit = 0;
+  if (key != kEmpty) {
+    const uint64_t s = find_slot(tv, key);
+    if (s != ~0ull && tv.slots[s].c_old != 0) {
+      const ShState st = tv.sh[s];
+      const float k0 = 0.28209479177387814f, k1 = 0.4886025119029199f;
+      const float y = ((st.c[0] * k0 + st.c[1] * (k1 * q.ny[i])) + st.c[2] * (k1 * q.nz[i])) +
+                      st.c[3] * (k1 * q.nx[i]);
+      rgb[0] = (y + st.co) - st.cg;
+      rgb[1] = y + st.cg;
+      rgb[2] = (y - st.co) - st.cg;
+      hit = 1;
+    }
+  }
+  out[i] = rgb[0];
+  out[n + i] = rgb[1];
+  out[2 * n + i] = rgb[2];
+  if (found) found[i] = hit;
+}
+
+__global__ void k_compact_sh(TableView tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                             unsigned long long* keys, uint32_t* c_old, float* coeff) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    const Slot sl = tv.slots[s];
+    if (sl.key == kEmpty) continue;
+    const unsigned long long at = atomicAdd(cursor, 1ull);
+    if (at >= cap) continue;
+    keys[at] = sl.key;
+    c_old[at] = sl.c_old;
+    const ShState st = tv.sh[s];
+    const float v[6] = {st.c[0], st.c[1], st.c[2], st.c[3], st.co, st.cg};
+    for (int k = 0; k < 6; ++k) coeff[(uint64_t)k * cap + at] = v[k];
+  }
+}
+
+__global__ void k_clear_sh(TableView tv, uint64_t nslots) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    tv.sh[s] = ShState{};
+    tv.sh_acc[s] = ShAcc{};
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 static inline unsigned grid_for(uint64_t n, unsigned block) {
   uint64_t g = (n + block - 1) / block;
@@ -517,6 +716,36 @@ hipError_t launch_compact(const TableView& tv, uint64_t nslots, int32_t dtype,
                           uint32_t* n_new, uint32_t* c_old, float* rgb, hipStream_t s) {
   k_compact<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, dtype, cursor, cap, keys,
                                                           n_new, c_old, rgb);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_sh(const RecPtrs& rec, uint64_t n, const KeyParams& kp, const TableView& tv,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_insert_sh<<<grid_for(n, 256), 256, 0, s>>>(rec, n, kp, tv);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_sh(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s) {
+  k_update_sh<<<update_grid(nslots), 256, 0, s>>>(tv, bp, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_sh(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv, float* out,
+                           uint8_t* found, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_query_sh<<<grid_for(n, 256), 256, 0, s>>>(q, n, kp, tv, out, found);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_sh(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                             unsigned long long* keys, uint32_t* c_old, float* coeff, hipStream_t s) {
+  k_compact_sh<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, cursor, cap, keys, c_old, coeff);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_sh(const TableView& tv, uint64_t nslots, hipStream_t s) {
+  k_clear_sh<<<stride_grid(nslots, 256, 8192), 256, 0, s>>>(tv, nslots);
   return hipGetLastError();
 }
 

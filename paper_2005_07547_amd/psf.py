@@ -26,6 +26,7 @@ PSF_FLAG_TRANSPOSE_RUNS = 4
 PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 PSF_PRIM_QUAD, PSF_PRIM_SPHERE = 0, 1
+PSF_PAYLOAD_RGB, PSF_PAYLOAD_SH2_YCOCG = 0, 1
 PSF_PATHS_LO, PSF_PATHS_LOE = 0, 1
 PSF_ORIGIN_CAMERA, PSF_ORIGIN_POINT = 0, 1
 
@@ -52,6 +53,7 @@ class psf_config(ctypes.Structure):
         ("state_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("insert_mode", ctypes.c_int32), ("part_log2", ctypes.c_uint32),
         ("max_batch", ctypes.c_uint64), ("bin_per", ctypes.c_uint32), ("weighted", ctypes.c_uint32),
+        ("payload", ctypes.c_uint32),
     ]
 
 
@@ -135,6 +137,7 @@ EXPORTS = [
     ("psf_get_stats", ctypes.c_int, [_vp, _P(psf_stats), _vp]),
     ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_export_cells_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
+    ("psf_export_sh_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_batch_create", ctypes.c_int, [_u32, _P(_vp)]),
     ("psf_batch_destroy", ctypes.c_int, [_vp]),
     ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
@@ -177,7 +180,7 @@ def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_m
                 max_level=15, normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
                 alpha_mode=PSF_ALPHA_PAPER, alpha=0.2, t_max=5.0, state_dtype=PSF_STATE_F32,
                 flags=0, insert_mode=PSF_INSERT_AUTO, part_log2=0, max_batch=0, bin_per=0,
-                weighted=0, **_ignored):
+                weighted=0, payload=0, **_ignored):
     c = psf_config()
     c.log2_slots, c.max_probe = int(log2_slots), int(max_probe)
     c.cam[:] = [float(x) for x in cam]
@@ -187,6 +190,7 @@ def make_config(log2_slots=16, max_probe=64, cam=(0.0, 0.0, 0.0), kappa=0.0, e_m
     c.state_dtype, c.flags, c.insert_mode = int(state_dtype), int(flags), int(insert_mode)
     c.part_log2, c.max_batch, c.bin_per = int(part_log2), int(max_batch), int(bin_per)
     c.weighted = int(weighted)
+    c.payload = int(payload)
     return c
 
 
@@ -387,6 +391,26 @@ class Table:
             n_new, c_old = n_new.view(np.float32), c_old.view(np.float32)
         return {"keys": keys[:c][order], "n_new": n_new[:c][order], "c_old": c_old[:c][order],
                 "L": rgb[:, :c][:, order]}
+
+
+def export_sh(t):
+    """Occupied cells of an SH payload table: keys (uint64), c_old (uint32
+    counts; float32 weight sums for a weighted table), coeff (6 x C float32:
+    four luminance SH coefficients, Co, Cg), sorted by key."""
+    import numpy as np
+    st = t.stats()
+    cap = max(1, int(st["occupied"]))
+    keys = np.zeros(cap, dtype=np.uint64)
+    c_old = np.zeros(cap, dtype=np.uint32)
+    coeff = np.zeros((6, cap), dtype=np.float32)
+    count = ctypes.c_uint64()
+    _check(t._lib.psf_export_sh_cells(t.handle, keys.ctypes.data, c_old.ctypes.data, coeff.ctypes.data, cap,
+                                      ctypes.byref(count), current_stream()))
+    c = int(count.value)
+    order = np.argsort(keys[:c], kind="stable")
+    if t.cfg.weighted:
+        c_old = c_old.view(np.float32)
+    return {"keys": keys[:c][order], "c_old": c_old[:c][order], "coeff": coeff[:, :c][:, order]}
 
 
 def estimate(t_oe, t_fli, a: dict, mode: int, param: float, out=None, applied=None):
