@@ -55,10 +55,12 @@ KERNEL_SYMBOL = {"bin": "k_bin", "merge_blend": "k_merge", "query": "k_unstage",
                  "merge": "k_merge", "update": "k_update", "insert_direct": "k_insert_direct"}
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, key: str = "bytes"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary (profiles/traffic_<workload>.json), or None when there is none or
-    the kernel sources changed since it was taken."""
+    summary (profiles/traffic_<workload>.json; key "bytes": FETCH_SIZE at the
+    streaming copy's scale, "bytes_random": at the random-gather scale), or
+    None when there is none or the kernel sources changed since it was
+    taken."""
     from paper_2005_07547_amd import profiling
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
@@ -71,7 +73,7 @@ def measured_traffic(workload: str, kernel: str):
     # rocprofv3 records demangled names ("void psf::k_merge<true>(...)")
     pat = re.compile(r"(^|[\s:])" + re.escape(sym) + r"[<(]")
     hits = [v for name, v in rec["kernels"].items() if pat.search(name)]
-    return int(hits[0]["bytes"]) if len(hits) == 1 else None
+    return int(hits[0][key]) if len(hits) == 1 and key in hits[0] else None
 
 
 def _oracle_rate(orc, rec, budget_s):
@@ -577,6 +579,9 @@ def main():
                     help="library default launch parameters instead of the recorded tuned ones")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--gather-calib", action="store_true",
+                    help="run only random row gathers of known bytes (32, 64 and 128-byte rows from a "
+                         "4 GiB table; calibrates HBM byte counters for random requests)")
     args = ap.parse_args()
     TUNED["use"] = not args.untuned
 
@@ -602,6 +607,27 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes,
                           "launches": 3}), flush=True)
+        return
+    if args.gather_calib:
+        # 2^24 rows gathered per launch at seeded random row indices from a
+        # table far larger than the L2 and the Infinity Cache; each launch
+        # reads rows * row_bytes of the table plus 8-byte indices and writes
+        # rows * row_bytes.  One launch per row width, in order 32, 64, 128.
+        rows = 1 << 24
+        table = torch.ones(1 << 30, dtype=torch.float32, device=dev)  # 4 GiB
+        g = torch.Generator(device="cpu").manual_seed(12345)
+        out = {}
+        for row_bytes in (32, 64, 128):
+            width = row_bytes // 4
+            view = table.view(-1, width)
+            idx = torch.randint(0, view.shape[0], (rows,), generator=g).to(dev)
+            torch.cuda.synchronize()
+            got = torch.index_select(view, 0, idx)
+            torch.cuda.synchronize()
+            out[row_bytes] = {"rows": rows, "table_bytes_read": rows * row_bytes, "index_bytes_read": rows * 8,
+                              "bytes_written": rows * row_bytes, "checksum": float(got.sum())}
+            del got, idx
+        print(json.dumps({"gather_calib": out}), flush=True)
         return
     wl = _workload(args.workload)
     sc = W.make_scene(wl)
@@ -692,6 +718,7 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(wl["name"], dom),
+                    "traffic_random_scale": measured_traffic(wl["name"], dom, "bytes_random"),
                     "algorithmic_bytes_per_launch": int(per_launch),
                     "avg_launch_ms": round(kernels[dom]["avg_ms"], 5)}
     iter_gbs = ab["iteration"] / (elapsed / steps) / 1e9

@@ -9,8 +9,11 @@
 * ``traffic``: combine two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE, KiB
   per dispatch) with the same counters taken on a plain 1 GiB device copy,
   into per-launch HBM bytes of each kernel, scaled so that the copy reads
-  and writes exactly its size.  The record carries a digest of the kernel
-  sources; a consumer treats it as stale once the sources change.
+  and writes exactly its size; with FETCH_SIZE taken on random row gathers
+  of known size as well, also scaled as random line fills need (the copy's
+  scale counts a streamed 128-byte request at half its size, a random line
+  fill at its size).  The record carries a digest of the kernel sources; a
+  consumer treats it as stale once the sources change.
 
 Usage: python -m paper_2005_07547_amd.profiling stats|traffic ... (see --help).
 """
@@ -54,19 +57,50 @@ def counter_means(d: str) -> dict:
     return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
 
 
-def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir) -> dict:
+GATHER_ROWS = 1 << 24       # rows per gather launch of bench.py --gather-calib
+GATHER_ROW_BYTES = (32, 64, 128)
+
+
+def gather_fetch_scale(gather_fetch_dir: str, copy_fetch_scale: float) -> dict:
+    """FETCH_SIZE scale for random line fills, from bench.py --gather-calib:
+    the 128-byte-row gather reads exactly 2^24 random 128-byte lines (no
+    partial-line ambiguity) plus its 8-byte indices as a stream (counted at
+    the copy's scale).  Also the bytes counted per row for every width."""
+    rows = list(csv.DictReader(open(_find(gather_fetch_dir, "*counter_collection.csv"))))
+    g = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows
+               if "gather" in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE")
+    if len(g) != len(GATHER_ROW_BYTES):
+        raise ValueError(f"expected {len(GATHER_ROW_BYTES)} gather dispatches, found {len(g)}")
+    index_kib = GATHER_ROWS * 8 / 1024 / copy_fetch_scale
+    per_row = {w: (kib - index_kib) * 1024 / GATHER_ROWS for w, (_, kib) in zip(GATHER_ROW_BYTES, g)}
+    scale = GATHER_ROW_BYTES[-1] / per_row[GATHER_ROW_BYTES[-1]]
+    return {"random_fetch_scale": scale, "fetch_bytes_counted_per_random_row": per_row}
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, gather_fetch_dir=None) -> dict:
+    """HBM bytes per launch of every kernel.  `bytes` scales FETCH_SIZE as the
+    streaming copy needs (right for streamed reads); with a gather
+    calibration, `bytes_random` scales it as random line fills need (right
+    for scattered reads); a kernel's real traffic lies between the two."""
     f, w = counter_means(fetch_dir), counter_means(write_dir)
     cf_raw, cw_raw = counter_means(copy_fetch_dir), counter_means(copy_write_dir)
     copy_k = max(cf_raw, key=lambda k: cf_raw[k].get("FETCH_SIZE", 0))
     cf = COPY_BYTES / (cf_raw[copy_k]["FETCH_SIZE"] * 1024)
     cw = COPY_BYTES / (cw_raw[copy_k]["WRITE_SIZE"] * 1024)
+    gcal = gather_fetch_scale(gather_fetch_dir, cf) if gather_fetch_dir else None
     kernels = {}
     for k in f:
         if k in w and "FETCH_SIZE" in f[k] and "WRITE_SIZE" in w[k]:
-            kernels[k] = {"fetch_kib": f[k]["FETCH_SIZE"], "write_kib": w[k]["WRITE_SIZE"],
-                          "bytes": (f[k]["FETCH_SIZE"] * cf + w[k]["WRITE_SIZE"] * cw) * 1024}
-    return {"digest": source_digest(), "fetch_scale": cf, "write_scale": cw,
-            "copy_kernel": copy_k, "kernels": kernels}
+            rec = {"fetch_kib": f[k]["FETCH_SIZE"], "write_kib": w[k]["WRITE_SIZE"],
+                   "bytes": (f[k]["FETCH_SIZE"] * cf + w[k]["WRITE_SIZE"] * cw) * 1024}
+            if gcal:
+                rec["bytes_random"] = (f[k]["FETCH_SIZE"] * gcal["random_fetch_scale"] + w[k]["WRITE_SIZE"] * cw) * 1024
+            kernels[k] = rec
+    out = {"digest": source_digest(), "fetch_scale": cf, "write_scale": cw,
+           "copy_kernel": copy_k, "kernels": kernels}
+    if gcal:
+        out.update(gcal)
+    return out
 
 
 def stats_markdown(stats_csv: str, title: str, command: str, note: str = "") -> str:
@@ -109,15 +143,25 @@ def traffic_markdown(rec: dict, title: str, commands: list, algorithmic: dict) -
     lines = [f"# {title}", "", "Counters (KiB per dispatch), each in a rocprofv3 run of its own:", ""]
     lines += [f"    {c}" for c in commands]
     lines += ["", f"Calibration on a 1 GiB device copy: FETCH_SIZE x {rec['fetch_scale']:.4f}, "
-              f"WRITE_SIZE x {rec['write_scale']:.4f} give the bytes the copy moves.", "",
-              "| Kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes (scaled) | Algorithmic bytes | Ratio |",
-              "|---|---|---|---|---|---|"]
+              f"WRITE_SIZE x {rec['write_scale']:.4f} give the bytes the copy moves (streamed)."]
+    rnd = "random_fetch_scale" in rec
+    if rnd:
+        per = ", ".join(f"{w} B rows: {b:.0f} B" for w, b in rec["fetch_bytes_counted_per_random_row"].items())
+        lines += [f"Calibration on random row gathers (2^24 rows from a 4 GiB table): FETCH_SIZE counts per "
+                  f"row {per}; the 128-byte rows (whole lines) give FETCH_SIZE x {rec['random_fetch_scale']:.4f} "
+                  "for random line fills.  A kernel's real traffic lies between the random-scaled and the "
+                  "copy-scaled bytes, by its share of streamed reads."]
+    lines += ["", "| Kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes, copy scale | "
+              + ("HBM bytes, random scale | " if rnd else "") + "Algorithmic bytes | Ratio |",
+              "|---|---|---|---|" + ("---|" if rnd else "") + "---|---|"]
     for name, v in sorted(rec["kernels"].items(), key=lambda kv: -kv[1]["bytes"]):
         short = name.split("(")[0].split("::")[-1]
         base = short.split("<")[0]
         a = algorithmic.get(base)
+        ratio = (f"{v['bytes_random'] / a:.2f} - {v['bytes'] / a:.2f}" if rnd else f"{v['bytes'] / a:.2f}") if a else "-"
         lines.append(f"| {short} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['bytes'] / 1e6:.1f} MB | "
-                     + (f"{a / 1e6:.1f} MB | {v['bytes'] / a:.2f} |" if a else "- | - |"))
+                     + (f"{v['bytes_random'] / 1e6:.1f} MB | " if rnd else "")
+                     + (f"{a / 1e6:.1f} MB | {ratio} |" if a else "- | - |"))
     lines += ["", f"Kernel source digest: `{rec['digest']}` (bench.py reports `traffic` only while the "
               "kernel sources still have this digest)."]
     return "\n".join(lines) + "\n"
@@ -135,6 +179,7 @@ def main():
     b = sub.add_parser("traffic")
     for name in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument(f"--{name}", required=True)
+    b.add_argument("--gather-fetch", default=None)
     b.add_argument("--command", default="")
     b.add_argument("--out", required=True)
     m = sub.add_parser("counters-md")
@@ -165,7 +210,7 @@ def main():
         with open(args.out, "w") as f:
             f.write(md)
     else:
-        rec = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write)
+        rec = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.gather_fetch)
         rec["command"] = args.command
         with open(args.out, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
