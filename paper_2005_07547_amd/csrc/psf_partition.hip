@@ -507,63 +507,80 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     }
     loaded = c0;
   };
+  // A chunk: the runs of up to 64 * kRunsPerLane consecutive tiles of the
+  // wave's slice, lane l holding kRunsPerLane of them; pk[j] packs the start
+  // of the lane's run j among the lane's entries (< 3 tiles) with the run's
+  // offset in its tile (< 2^16); excl is the lane's first entry in the
+  // chunk, total the chunk's entries.
+  struct Chunk {
+    uint32_t pk[kRunsPerLane];
+    uint32_t excl, total;
+    uint64_t cbase;
+  };
+  auto chunk_of = [&](uint32_t c0) {
+    if (loaded != c0) load_runs(c0);
+    Chunk ch;
+    uint32_t lt = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kRunsPerLane; ++j) {
+      ch.pk[j] = (lt << 16) | r_lo[j];
+      lt += r_hi[j] - r_lo[j];
+    }
+    uint32_t inc = lt;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
+      if (lane >= off) inc += v;
+    }
+    ch.excl = inc - lt;
+    ch.total = (uint32_t)__shfl((int)inc, 63);
+    ch.cbase = (uint64_t)c0 * tile;
+    return ch;
+  };
+  // The batch at entry e0 of a chunk: at[q] is the staging index of the
+  // lane's q-th entry, ev[q] whether it exists (absent entries point at a
+  // tile's first entry, so that every load stays branch-free and in
+  // bounds).  A batch takes the next 64 * kEntryBatch entries of the
+  // chunk's concatenated runs.
+  auto batch_of = [&](const Chunk& ch, uint32_t e0, uint64_t* at, bool* ev) {
+#pragma unroll
+    for (uint32_t q = 0; q < kEntryBatch; ++q) {
+      const uint32_t e = e0 + q * 64 + lane;
+      const uint32_t a = wave_upper_bound(ch.excl, e);
+      const uint32_t r = e - (uint32_t)__shfl((int)ch.excl, (int)a);
+      // the last of lane a's runs that starts at or before r holds it
+      uint32_t js = 0, ps = (uint32_t)__shfl((int)ch.pk[0], (int)a);
+#pragma unroll
+      for (uint32_t j = 1; j < kRunsPerLane; ++j) {
+        const uint32_t v = (uint32_t)__shfl((int)ch.pk[j], (int)a);
+        if ((v >> 16) <= r) {
+          js = j;
+          ps = v;
+        }
+      }
+      ev[q] = e < ch.total;
+      at[q] = ch.cbase + (ev[q] ? (uint64_t)(a * kRunsPerLane + js) * tile + (ps & 0xffffu) + (r - (ps >> 16))
+                                : 0ull);
+    }
+  };
   // Calls body(at, ev, nb) for every batch of the wave's entries, in order
-  // (nb counts batches): at[q] is the staging index of the lane's q-th
-  // entry, ev[q] whether it exists (absent entries point at a tile's first
-  // entry, so that every load stays branch-free and in bounds).  A batch
-  // takes the next 64 * kEntryBatch entries of the chunk's concatenated runs.
+  // (nb counts batches).
   auto for_each_batch = [&](auto&& body) {
     uint32_t nb = 0;
     for (uint32_t c0 = w_lo; c0 < w_hi; c0 += 64 * kRunsPerLane) {
-      if (loaded != c0) load_runs(c0);
-      // start of each of the lane's runs among the lane's entries (< 3 tiles)
-      // packed with the run's offset in its tile (< 2^16)
-      uint32_t pk[kRunsPerLane];
-      uint32_t lt = 0;
-#pragma unroll
-      for (uint32_t j = 0; j < kRunsPerLane; ++j) {
-        pk[j] = (lt << 16) | r_lo[j];
-        lt += r_hi[j] - r_lo[j];
-      }
-      uint32_t inc = lt;
-#pragma unroll
-      for (uint32_t off = 1; off < 64; off <<= 1) {
-        const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
-        if (lane >= off) inc += v;
-      }
-      const uint32_t excl = inc - lt;
-      const uint32_t total = (uint32_t)__shfl((int)inc, 63);
-      const uint64_t cbase = (uint64_t)c0 * tile;
-      for (uint32_t e0 = 0; e0 < total; e0 += 64 * kEntryBatch, ++nb) {
+      const Chunk ch = chunk_of(c0);
+      for (uint32_t e0 = 0; e0 < ch.total; e0 += 64 * kEntryBatch, ++nb) {
         bool ev[kEntryBatch];
         uint64_t at[kEntryBatch];
-#pragma unroll
-        for (uint32_t q = 0; q < kEntryBatch; ++q) {
-          const uint32_t e = e0 + q * 64 + lane;
-          const uint32_t a = wave_upper_bound(excl, e);
-          const uint32_t r = e - (uint32_t)__shfl((int)excl, (int)a);
-          // the last of lane a's runs that starts at or before r holds it
-          uint32_t js = 0, ps = (uint32_t)__shfl((int)pk[0], (int)a);
-#pragma unroll
-          for (uint32_t j = 1; j < kRunsPerLane; ++j) {
-            const uint32_t v = (uint32_t)__shfl((int)pk[j], (int)a);
-            if ((v >> 16) <= r) {
-              js = j;
-              ps = v;
-            }
-          }
-          ev[q] = e < total;
-          at[q] = cbase + (ev[q] ? (uint64_t)(a * kRunsPerLane + js) * tile + (ps & 0xffffu) +
-                                       (r - (ps >> 16))
-                                 : 0ull);
-        }
+        batch_of(ch, e0, at, ev);
         body(at, ev, nb);
       }
     }
     return nb;
   };
 
-  // keys first, then the first runs: both in flight together
+  // keys first, then the first runs, then the wave's first batch of entries:
+  // all in flight together, before the key table is built
   constexpr uint32_t kKeysPerThread = (1u << kMaxPartLog2) / kMergeThreads;
   unsigned long long kk[kKeysPerThread];
 #pragma unroll
@@ -571,7 +588,20 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     const uint32_t s = tid + j * kMergeThreads;
     kk[j] = s < B ? tv.keys[base + s] : kEmpty;
   }
-  if (w_lo < w_hi) load_runs(w_lo);
+  Chunk ch0{};
+  uint64_t at0[kEntryBatch];
+  bool ev0[kEntryBatch];
+  unsigned long long ek0[kEntryBatch];
+  float4 v0[kEntryBatch];
+  if (w_lo < w_hi) {
+    ch0 = chunk_of(w_lo);
+    batch_of(ch0, 0, at0, ev0);
+#pragma unroll
+    for (uint32_t q = 0; q < kEntryBatch; ++q) {
+      ek0[q] = pv.stage_key[at0[q]];
+      v0[q] = pv.stage_v[at0[q]];
+    }
+  }
 #pragma unroll
   for (uint32_t j = 0; j < kKeysPerThread; ++j) {
     const uint32_t s = tid + j * kMergeThreads;
@@ -593,14 +623,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) keep_at[b][q] = keep_slot[b][q] = ~0u;
 
-  const uint32_t batches = for_each_batch([&](const uint64_t* at, const bool* ev, uint32_t nb) {
-    unsigned long long ek[kEntryBatch];
-    float4 v[kEntryBatch];
-#pragma unroll
-    for (uint32_t q = 0; q < kEntryBatch; ++q) {
-      ek[q] = pv.stage_key[at[q]];
-      v[q] = pv.stage_v[at[q]];
-    }
+  auto accumulate = [&](const uint64_t* at, const bool* ev, const unsigned long long* ek, const float4* v,
+                        uint32_t nb) {
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       uint32_t slot = ~0u;
@@ -646,7 +670,23 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         }
       }
     }
-  });
+  };
+  // the first batch was loaded above; every later one into the same registers
+  uint32_t batches = 0;
+  for (uint32_t c0 = w_lo; c0 < w_hi; c0 += 64 * kRunsPerLane) {
+    const Chunk ch = c0 == w_lo ? ch0 : chunk_of(c0);
+    for (uint32_t e0 = 0; e0 < ch.total; e0 += 64 * kEntryBatch, ++batches) {
+      if (c0 != w_lo || e0 != 0) {
+        batch_of(ch, e0, at0, ev0);
+#pragma unroll
+        for (uint32_t q = 0; q < kEntryBatch; ++q) {
+          ek0[q] = pv.stage_key[at0[q]];
+          v0[q] = pv.stage_v[at0[q]];
+        }
+      }
+      accumulate(at0, ev0, ek0, v0, batches);
+    }
+  }
   __syncthreads();
 
   // write the partition back; the old slots of a group are loaded together
