@@ -11,7 +11,10 @@ function, with optional per-record MIS weights: Sec. 2.5), Sec. 2.4 Eq. 10-11
 out in ``psf_oracle.cpp``), Algorithm 1 (lookups read the last blended state),
 and, for the two-field estimators, Sec. 2.5, Sec. 4.2 (Eq. 25) and Sec. 5
 (Eq. 28) in ``estimate`` below (plain numpy in binary64 over the lookups);
-``ShOracle`` holds the two-band SH YCoCg cell payload of Sec. 2.6.
+``ShOracle`` holds the two-band SH YCoCg cell payload of Sec. 2.6.  Every
+cell also keeps a luminance variance around its approximant (the paper
+defines none; the reading is stated in ``psf_oracle.cpp`` and pinned in
+``tests/test_oracle_variance.py``).
 """
 from __future__ import annotations
 
@@ -67,6 +70,10 @@ def _load():
     lib.orc_export.restype = u64
     lib.orc_export.argtypes = [vp, vp, vp, vp, vp, vp, u64]
     lib.orc_counters.argtypes = [vp, vp, vp, vp]
+    lib.orc_export_variance.restype = u64
+    lib.orc_export_variance.argtypes = [vp, vp, vp, u64]
+    lib.orc_sharded_export_variance.restype = u64
+    lib.orc_sharded_export_variance.argtypes = [vp, vp, vp, u64]
     lib.orc_sharded_create.restype = vp
     lib.orc_sharded_create.argtypes = [u32] + lib.orc_create.argtypes
     lib.orc_sharded_destroy.argtypes = [vp]
@@ -219,6 +226,19 @@ class Oracle:
             n_new, c_old = n_new.astype(np.uint64), c_old.astype(np.uint64)
         return {"keys": keys, "n_new": n_new, "c_old": c_old, "L": L, "s": s}
 
+    def export_variance(self):
+        """Keys (ascending) and each cell's luminance variance around its
+        approximant (the mixture variance under the blend's weights)."""
+        cap = self.count()
+        keys = np.zeros(cap, dtype=np.uint64)
+        var = np.zeros(cap, dtype=np.float64)
+        if cap:
+            assert self._export_variance(keys.ctypes.data, var.ctypes.data, cap) == cap
+        return keys, var
+
+    def _export_variance(self, keys, var, cap):
+        return self._lib.orc_export_variance(self._h, keys, var, cap)
+
     def counters(self):
         a = np.zeros(3, dtype=np.uint64)
         self._lib.orc_counters(self._h, a[0:].ctypes.data, a[1:].ctypes.data, a[2:].ctypes.data)
@@ -229,7 +249,8 @@ class ShardedOracle(Oracle):
     """The same table split by key over `threads` host threads (one std::map
     per thread; a cell's samples arrive in array order on its own thread, so
     the results equal the single-threaded oracle's bit for bit).  Supports
-    insert, update, query, set_filter, export, count, counters and keys."""
+    insert, update, query, set_filter, export, export_variance, count,
+    counters and keys."""
 
     def __init__(self, threads: int, cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=0, max_level=15,
                  normal_bins_log2=2, dir_bins_log2=3, rough_thr=0.3,
@@ -290,6 +311,9 @@ class ShardedOracle(Oracle):
         if not self.weighted:
             n_new, c_old = n_new.astype(np.uint64), c_old.astype(np.uint64)
         return {"keys": keys, "n_new": n_new, "c_old": c_old, "L": L, "s": s}
+
+    def _export_variance(self, keys, var, cap):
+        return self._lib.orc_sharded_export_variance(self._s, keys, var, cap)
 
     def counters(self):
         a = np.zeros(3, dtype=np.uint64)

@@ -32,6 +32,18 @@
 //     implementation obtains the same bits.
 //   * Algorithm 1: a lookup of the approximant at a vertex reads the state
 //     left by the last completed temporal blend.
+//   * Per-cell luminance variance (the paper defines none; this project's
+//     reading): the spread of the cell's samples around the approximant,
+//     under the same temporal weights.  With Y = (r + 2 g + b) / 4 (the
+//     luminance of the YCoCg decomposition of Sec. 2.6), the blend of Eq.
+//     10-11 makes the approximant's luminance the mixture mean of the
+//     frames' sample distributions with weights beta_j (frame j's alpha
+//     times (1 - alpha) of every later frame); the variance kept is that
+//     mixture's variance, i.e. the population variance of every sample so
+//     far, sample i of frame j weighted beta_j w_i / c_j.  One frame updates
+//     it as a two-component mixture: V <- (1 - a) V + a s2 + a (1 - a)
+//     (m - mu)^2 with m, s2 the frame's weighted mean and variance of Y and
+//     mu the luminance of the approximant before the blend.
 //
 // Accumulation and blending are in binary64.  The table is a std::map with no
 // capacity limit.  A key-sharded variant (orc_sharded_*, at the end) runs
@@ -65,9 +77,14 @@ struct Config {
 struct Cell {
   double n_new = 0.0;            // c_h^new of the current frame (sum of weights)
   double s[3] = {0.0, 0.0, 0.0}; // sum of the frame's weighted sample values
+  double q = 0.0;                // sum of the frame's weighted squared luminances
   double c_old = 0.0;            // cumulative counter up to the previous frame
   double L[3] = {0.0, 0.0, 0.0}; // approximant
+  double V = 0.0;                // luminance variance around the approximant
 };
+
+// Luminance of an RGB triple (Y of YCoCg).
+double luma(double r, double g, double b) { return ((r + 2.0 * g) + b) * 0.25; }
 
 struct Oracle {
   Config cfg;
@@ -300,6 +317,8 @@ static void accumulate(Oracle* o, uint64_t key, float R, float G, float B, float
   c.s[0] += wd * (double)R;
   c.s[1] += wd * (double)G;
   c.s[2] += wd * (double)B;
+  const double y = luma((double)R, (double)G, (double)B);
+  c.q += wd * (y * y);
   o->inserted++;
 }
 
@@ -328,6 +347,13 @@ uint64_t orc_update(void* h) {
     Cell& c = kv.second;
     if (c.n_new == 0.0) continue;
     double a = alpha_of(o->cfg, c.n_new, c.c_old);
+    // the frame's weighted mean and variance of Y, the mixture update
+    const double m = luma(c.s[0], c.s[1], c.s[2]) / c.n_new;
+    double s2 = c.q / c.n_new - m * m;
+    if (s2 < 0.0) s2 = 0.0;
+    const double mu = luma(c.L[0], c.L[1], c.L[2]);
+    c.V = (1.0 - a) * c.V + a * s2 + a * (1.0 - a) * (m - mu) * (m - mu);
+    c.q = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
       double mean = c.s[ch] / c.n_new;
       c.L[ch] = (1.0 - a) * c.L[ch] + a * mean;
@@ -440,6 +466,19 @@ uint64_t orc_export(void* h, uint64_t* keys, double* n_new, double* c_old, doubl
       if (L) L[ch * cap + i] = kv.second.L[ch];
       if (s) s[ch * cap + i] = kv.second.s[ch];
     }
+    ++i;
+  }
+  return i;
+}
+
+// Cells in ascending key order with their luminance variance.
+uint64_t orc_export_variance(void* h, uint64_t* keys, double* var, uint64_t cap) {
+  Oracle* o = static_cast<Oracle*>(h);
+  uint64_t i = 0;
+  for (auto& kv : o->cells) {
+    if (i >= cap) break;
+    keys[i] = kv.first;
+    var[i] = kv.second.V;
     ++i;
   }
   return i;
@@ -610,6 +649,22 @@ uint64_t orc_sharded_export(void* h, uint64_t* keys, double* n_new, double* c_ol
       if (L) L[ch * cap + i] = c.L[ch];
       if (s_out) s_out[ch * cap + i] = c.s[ch];
     }
+    ++i;
+  }
+  return i;
+}
+
+// As orc_export_variance over every shard.
+uint64_t orc_sharded_export_variance(void* h, uint64_t* keys, double* var, uint64_t cap) {
+  Sharded* s = static_cast<Sharded*>(h);
+  std::map<uint64_t, double> all;
+  for (Oracle* o : s->shard)
+    for (auto& kv : o->cells) all.emplace(kv.first, kv.second.V);
+  uint64_t i = 0;
+  for (auto& kv : all) {
+    if (i >= cap) break;
+    keys[i] = kv.first;
+    var[i] = kv.second;
     ++i;
   }
   return i;
