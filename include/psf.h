@@ -98,11 +98,30 @@ enum {
 enum {
   PSF_FLAG_PROBE_STATS = 1u,   /* record a probe-length histogram */
   PSF_FLAG_TIMING = 2u,        /* bracket every kernel launch with HIP events */
-  PSF_FLAG_TRANSPOSE_RUNS = 4u /* partitioned insert: always transpose the
+  PSF_FLAG_TRANSPOSE_RUNS = 4u, /* partitioned insert: always transpose the
                                   per-tile run table before the merge pass
                                   (by default only tables of 2^22 entries
                                   or more are transposed) */
+  PSF_FLAG_TRACK_VARIANCE = 8u  /* keep a binary32 luminance variance per
+                                  cell (below); RGB payload, unweighted
+                                  tables only (NOT_SUPPORTED otherwise) */
 };
+
+/* Per-cell luminance variance (PSF_FLAG_TRACK_VARIANCE).  The paper keeps
+ * none; this library's reading: the spread of a cell's samples around its
+ * approximant under the temporal weights of Eq. 10-11.  With the luminance
+ * Y = (r + 2 g + b) / 4 (Y of YCoCg), each blend of a frame with n samples,
+ * luminance mean m and population variance s2 (both from binary64 sums of
+ * Y and Y^2, rounded once) updates, in binary32, with the frame's alpha and
+ * mu the luminance of the state the blend continues from:
+ *     V <- (1 - alpha) V + alpha (s2 + (1 - alpha) (m - mu)^2)
+ * (alpha = 1, a cell's first blend or one after a counter reset: V = s2).
+ * V is then the population variance of every sample the cell has blended,
+ * frame j's samples each weighted beta_j / n_j (beta_j the weight Eq. 10-11
+ * gives frame j's mean in the approximant).  Memory: 12 more bytes per slot.
+ * The partitioned insert stages every record as its own entry in such a
+ * table (no pre-merge of neighbouring duplicates) and its merge pass holds
+ * a further binary64 sum per slot in LDS (44 instead of 36 bytes). */
 
 /* Kernel kinds reported by psf_kernel_times. */
 enum {
@@ -154,8 +173,10 @@ typedef struct psf_config {
   int32_t insert_mode;       /* PSF_INSERT_* */
   uint32_t part_log2;        /* partitioned insert: log2 slots per partition
                                 (0 = default: 11, or 12 for tables of 2^25
-                                slots; else 8..12).  A table of more than
-                                8192 partitions takes the direct strategy. */
+                                slots; else 8..12; at most 11 with
+                                PSF_FLAG_TRACK_VARIANCE).  A table of more
+                                than 8192 partitions takes the direct
+                                strategy. */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M, at most 2^31); larger
                                 inserts are split */
@@ -367,6 +388,13 @@ psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_new, uint3
  * serialises them.  Synchronises stream. */
 psf_status psf_export_cells_noalloc(psf_table* t, uint64_t* keys, uint32_t* n_new, uint32_t* c_old,
                                     float* state_rgb, uint64_t cap, uint64_t* count, psf_stream stream);
+
+/* Luminance variance of every occupied cell (a table created with
+ * PSF_FLAG_TRACK_VARIANCE, else NOT_SUPPORTED): keys and variance into host
+ * arrays of capacity cap.  Pending frame sums are not included.  Otherwise
+ * as psf_export_cells.  Synchronises stream. */
+psf_status psf_export_variance(psf_table* t, uint64_t* keys, float* var, uint64_t cap, uint64_t* count,
+                               psf_stream stream);
 
 /* Export of an SH2_YCOCG table: keys, c_old and the six state numbers per
  * occupied cell into host arrays of capacity cap (coeff: 6 * cap floats,

@@ -144,7 +144,10 @@ bool validate(const psf_config* c, std::string* why) {
     return bad("state_dtype must be F32, F16, BF16, F16_EF or BF16_EF");
   if (c->insert_mode < 0 || c->insert_mode > 2) return bad("insert_mode must be AUTO, DIRECT or PARTITIONED");
   if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
-  if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS))
+  if ((c->flags & PSF_FLAG_TRACK_VARIANCE) && c->part_log2 == 12)
+    return bad("part_log2 must be at most 11 in a table that keeps the variance");
+  if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS |
+                             PSF_FLAG_TRACK_VARIANCE))
     return bad("unknown flags");
   if (c->max_batch > (1ull << 31)) return bad("max_batch must be <= 2^31");
   if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
@@ -154,7 +157,7 @@ bool validate(const psf_config* c, std::string* why) {
 }
 
 struct Layout {
-  size_t sh = 0, sh_acc = 0;
+  size_t sh = 0, sh_acc = 0, var = 0, acc_q = 0;
   size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_v = 0, runs = 0,
          runs_t = 0, perm = 0, total = 0;
   uint32_t part_log2 = 0;
@@ -168,8 +171,11 @@ Layout layout_of(const psf_config& c) {
   const uint64_t S = 1ull << c.log2_slots;
   // default partition width: 2^11 slots, wider for tables that would
   // otherwise exceed the binning pass's partition count
+  // (at most 2^11 with the variance's further LDS sum: 2^12 slots of 44
+  // bytes exceed a workgroup's LDS)
+  const uint32_t widest = (c.flags & PSF_FLAG_TRACK_VARIANCE) ? 11u : 12u;
   uint32_t def = kDefaultPartLog2;
-  while (def < 12 && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kMaxPartitions) ++def;
+  while (def < widest && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kMaxPartitions) ++def;
   L.part_log2 = c.part_log2 ? c.part_log2 : def;
   if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;
   const uint64_t P = 1ull << (c.log2_slots - L.part_log2);
@@ -190,6 +196,12 @@ Layout layout_of(const psf_config& c) {
     off = align_up(off + S * sizeof(psf::ShState), 256);
     L.sh_acc = off;
     off = align_up(off + S * sizeof(psf::ShAcc), 256);
+  }
+  if (c.flags & PSF_FLAG_TRACK_VARIANCE) {
+    L.var = off;
+    off = align_up(off + S * 4, 256);
+    L.acc_q = off;
+    off = align_up(off + S * 8, 256);
   }
   if (L.part) {
     const uint64_t tile = psf::bin_tile(c.bin_per ? c.bin_per : kDefaultBinPer);
@@ -339,6 +351,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if (cfg->payload == PSF_PAYLOAD_SH2_YCOCG &&
       (cfg->state_dtype != PSF_STATE_F32 || cfg->insert_mode == PSF_INSERT_PARTITIONED))
     return fail(PSF_NOT_SUPPORTED, "the SH payload takes F32 state and the direct insert strategy");
+  if ((cfg->flags & PSF_FLAG_TRACK_VARIANCE) && (cfg->payload != PSF_PAYLOAD_RGB || cfg->weighted))
+    return fail(PSF_NOT_SUPPORTED, "the luminance variance is kept for unweighted RGB tables only");
   const Layout L = layout_of(*cfg);
   if (device_buffer) {
     if (buffer_bytes < L.total)
@@ -369,6 +383,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   t->tv.acc = reinterpret_cast<psf::Acc*>(b + L.acc);
   t->tv.sh = L.sh ? reinterpret_cast<psf::ShState*>(b + L.sh) : nullptr;
   t->tv.sh_acc = L.sh_acc ? reinterpret_cast<psf::ShAcc*>(b + L.sh_acc) : nullptr;
+  t->tv.var = L.var ? reinterpret_cast<float*>(b + L.var) : nullptr;
+  t->tv.acc_q = L.acc_q ? reinterpret_cast<double*>(b + L.acc_q) : nullptr;
   t->tv.log2_slots = cfg->log2_slots;
   t->tv.part_log2 = L.part_log2;
   t->tv.max_probe = cfg->max_probe < (1u << L.part_log2) ? cfg->max_probe : (1u << L.part_log2);
@@ -685,6 +701,34 @@ PSF_API psf_status psf_export_cells(psf_table* t, uint64_t* keys, uint32_t* n_ne
     for (int ch = 0; ch < 3 && e == hipSuccess; ++ch)
       e = hipMemcpyAsync(state_rgb + ch * cap, drgb + ch * occ, occ * 4, hipMemcpyDeviceToHost, s);
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "export");
+}
+
+PSF_API psf_status psf_export_variance(psf_table* t, uint64_t* keys, float* var, uint64_t cap, uint64_t* count,
+                                       psf_stream stream) {
+  if (!t || !keys || !count) return fail(PSF_INVALID_ARGUMENT, "table, keys or count is NULL");
+  if (!t->tv.var) return fail(PSF_NOT_SUPPORTED, "the table keeps no variance (PSF_FLAG_TRACK_VARIANCE)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t->last = s;
+  uint64_t occ = 0;
+  psf_status st = count_occupied(t, s, &occ);
+  if (st != PSF_OK) return st;
+  *count = occ;
+  if (occ > cap) return fail(PSF_BUFFER_TOO_SMALL, "more occupied cells than cap");
+  if (occ == 0) return PSF_OK;
+  const size_t bytes = 256 + occ * 8 + occ * 4;
+  char* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc export scratch");
+  auto* cur = reinterpret_cast<unsigned long long*>(d);
+  auto* dk = reinterpret_cast<unsigned long long*>(d + 256);
+  auto* dv = reinterpret_cast<float*>(d + 256 + occ * 8);
+  e = psf::launch_zero(cur, 16, s);
+  if (e == hipSuccess) e = psf::launch_compact_var(t->tv, nslots(t), cur, occ, dk, dv, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(keys, dk, occ * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && var) e = hipMemcpyAsync(var, dv, occ * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "export");

@@ -97,6 +97,8 @@ struct TableView {
   ShAcc* sh_acc;
   DevStats* stats;
   BlockTouch* touch;         // kTouchEntries
+  float* var;                // luminance variance per slot (PSF_FLAG_TRACK_VARIANCE, else null)
+  double* acc_q;             // the frame's sum of squared luminances per slot (idem)
   uint32_t log2_slots;
   uint32_t part_log2;        // slots per partition = 2^part_log2 (<= log2_slots)
   uint32_t max_probe;
@@ -117,6 +119,32 @@ __device__ __forceinline__ float counter_value(uint32_t c, bool wtd) {
 __device__ __forceinline__ uint32_t counter_add(uint32_t c, uint32_t n, bool wtd) {
   return wtd ? __float_as_uint(__uint_as_float(c) + __uint_as_float(n)) : c + n;
 }
+
+// Per-cell luminance variance (tables created with PSF_FLAG_TRACK_VARIANCE).
+// A sample's luminance is Y of YCoCg, (r + 2 g + b) / 4, in binary64.
+__device__ __forceinline__ double luma64(double r, double g, double b) { return ((r + 2.0 * g) + b) * 0.25; }
+
+// The frame's luminance mean m and population variance s2 from its sums
+// (channel sums s0..s2, squared-luminance sum q, n samples) in binary64.
+__device__ __forceinline__ void frame_moments(double s0, double s1, double s2, double q, double n, double& m,
+                                              double& var) {
+  m = luma64(s0, s1, s2) / n;
+  var = q / n - m * m;
+  if (var < 0.0) var = 0.0;
+}
+
+// One blend of the variance (binary32): the two-component mixture of the
+// cells' samples so far (weight 1 - alpha, variance V around mu, the
+// luminance of the state the blend continues from) and the frame's (weight
+// alpha, mean m, variance s2).
+__device__ __forceinline__ float blend_variance(float V, float alpha, float mu, double m, double s2) {
+  const float sf = (float)s2;
+  if (alpha == 1.0f) return sf;
+  const float d = (float)m - mu;
+  return (1.0f - alpha) * V + alpha * (sf + (1.0f - alpha) * (d * d));
+}
+
+__device__ __forceinline__ float luma32(float r, float g, float b) { return ((r + 2.0f * g) + b) * 0.25f; }
 
 struct BlendParams {
   int32_t mode;     // 0 Eq. 11, 1 constant alpha, 2 linear

@@ -157,6 +157,8 @@ hipError_t launch_insert_sh(const RecPtrs& rec, uint64_t n, const KeyParams& kp,
 hipError_t launch_update_sh(const TableView& tv, const BlendParams& bp, uint64_t nslots, hipStream_t s);
 hipError_t launch_query_sh(const QryPtrs& q, uint64_t n, const KeyParams& kp, const TableView& tv, float* out,
                            uint8_t* found, hipStream_t s);
+hipError_t launch_compact_var(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                              unsigned long long* keys, float* var, hipStream_t s);
 hipError_t launch_compact_sh(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
                              unsigned long long* keys, uint32_t* c_old, float* coeff, hipStream_t s);
 hipError_t launch_clear_sh(const TableView& tv, uint64_t nslots, hipStream_t s);

@@ -76,7 +76,8 @@ __global__ void __launch_bounds__(256) k_keys(RecPtrs rec, uint64_t n, KeyParams
 // lane as leader; sums are merged in LDS; each leader claims its slot with a
 // 64-bit CAS and adds the merged count and sums with global atomics.  In a
 // weighted table the sums are of w * value and the counter adds the weights
-// (binary32 atomics on the counter word).
+// (binary32 atomics on the counter word).  A table that keeps the luminance
+// variance also adds each sample's squared luminance (binary64) to acc_q.
 constexpr int kInsBlock = 256;
 
 __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64_t n, KeyParams kp,
@@ -84,6 +85,7 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   __shared__ float s_sum[kInsBlock][3];
   __shared__ uint32_t s_cnt[kInsBlock];
   __shared__ float s_w[kInsBlock];
+  __shared__ double s_q[kInsBlock];
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
@@ -93,6 +95,7 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   s_sum[tid][0] = s_sum[tid][1] = s_sum[tid][2] = 0.0f;
   s_cnt[tid] = 0;
   s_w[tid] = 0.0f;
+  s_q[tid] = 0.0;
   const bool wtd = weighted(tv);
   __syncthreads();
 
@@ -143,6 +146,10 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
     atomicAdd(&s_sum[wbase + leader][0], r);
     atomicAdd(&s_sum[wbase + leader][1], g);
     atomicAdd(&s_sum[wbase + leader][2], b);
+    if (tv.acc_q) {
+      const double y = luma64(r, g, b);
+      atomicAdd(&s_q[wbase + leader], y * y);
+    }
   }
   __syncthreads();
 
@@ -162,6 +169,7 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
       atomicAdd(&a->s[0], s_sum[tid][0]);
       atomicAdd(&a->s[1], s_sum[tid][1]);
       atomicAdd(&a->s[2], s_sum[tid][2]);
+      if (tv.acc_q) atomicAdd(&tv.acc_q[slot], s_q[tid]);
       if (stats) atomicAdd(&s_hist[probes - 1 < 15 ? probes - 1 : 15], 1u);
     } else {
       atomicAdd(&tv.stats->dropped, (unsigned long long)cnt);
@@ -194,6 +202,12 @@ __device__ __forceinline__ bool blend_slot(const TableView& tv, const BlendParam
   }
   uint32_t enc[4], pad;
   encode_state(bp.dtype, out[0], out[1], out[2], enc, pad, sat);
+  if (tv.var) {
+    double m, s2;
+    frame_moments(a.s[0], a.s[1], a.s[2], tv.acc_q[s], (double)a.n, m, s2);
+    tv.var[s] = blend_variance(tv.var[s], alpha, luma32(L[0], L[1], L[2]), m, s2);
+    tv.acc_q[s] = 0.0;
+  }
   d->c_old = counter_add(c_old, a.n, wtd);
   d->pad = pad;
   *reinterpret_cast<uint4*>(d->L) = make_uint4(enc[0], enc[1], enc[2], enc[3]);
@@ -342,6 +356,10 @@ __global__ void k_clear(TableView tv, uint64_t nslots) {
     tv.slots[s] = z;
     tv.keys[s] = kEmpty;
     tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
+    if (tv.var) {
+      tv.var[s] = 0.0f;
+      tv.acc_q[s] = 0.0;
+    }
   }
 }
 
@@ -609,6 +627,19 @@ __global__ void k_compact_sh(TableView tv, uint64_t nslots, unsigned long long* 
   }
 }
 
+__global__ void k_compact_var(TableView tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                              unsigned long long* keys, float* var) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    const unsigned long long k = tv.slots[s].key;
+    if (k == kEmpty) continue;
+    const unsigned long long at = atomicAdd(cursor, 1ull);
+    if (at >= cap) continue;
+    keys[at] = k;
+    var[at] = tv.var[s];
+  }
+}
+
 __global__ void k_clear_sh(TableView tv, uint64_t nslots) {
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
        s += (uint64_t)gridDim.x * blockDim.x) {
@@ -741,6 +772,12 @@ hipError_t launch_query_sh(const QryPtrs& q, uint64_t n, const KeyParams& kp, co
 hipError_t launch_compact_sh(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
                              unsigned long long* keys, uint32_t* c_old, float* coeff, hipStream_t s) {
   k_compact_sh<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, cursor, cap, keys, c_old, coeff);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_var(const TableView& tv, uint64_t nslots, unsigned long long* cursor, uint64_t cap,
+                              unsigned long long* keys, float* var, hipStream_t s) {
+  k_compact_var<<<stride_grid(nslots, 256, 4096), 256, 0, s>>>(tv, nslots, cursor, cap, keys, var);
   return hipGetLastError();
 }
 

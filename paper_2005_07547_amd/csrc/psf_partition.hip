@@ -145,8 +145,9 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
   const bool wtd = weighted(tv);
-  // records merge into runs only with integer counters and no weights
-  const bool premerge = !kW;
+  // records merge into runs only with integer counters and no weights, and
+  // not where the merge needs each sample's own squared luminance
+  const bool premerge = !kW && !tv.var;
   for (uint32_t p = tid; p <= P; p += kBinThreads) s_hist[p] = 0;
   __syncthreads();
 
@@ -443,8 +444,10 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
                                            const BlendParams& bp, uint32_t blk, bool results) {
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
   // than f32 ones on gfx950 and exact enough to make the sum order
-  // immaterial).  After the blend the sums hold the cells' new values.  In
-  // a weighted table cnt holds binary32 weight sums.
+  // immaterial), then, in a table that keeps the luminance variance,
+  // sumq[B] (the squared luminances; every entry is one record there).
+  // After the blend the sums hold the cells' new values.  In a weighted
+  // table cnt holds binary32 weight sums.
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
@@ -461,6 +464,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   double* s_sum0 = reinterpret_cast<double*>(s_cnt + B);  // B >= 256: 8-byte aligned
   double* s_sum1 = s_sum0 + B;
   double* s_sum2 = s_sum1 + B;
+  double* s_sumq = s_sum2 + B;  // only with tv.var
+  const bool var = tv.var != nullptr;
   const uint32_t tile = pv.tile;
   if (!kFused) results = false;
 
@@ -609,6 +614,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       s_key[s] = kk[j];
       s_cnt[s] = 0;
       s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0;
+      if (var) s_sumq[s] = 0.0;
     }
   }
   if (tid == 0) s_dropped = s_touched = s_sat = 0;
@@ -657,6 +663,10 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           atomicAdd(&s_sum0[slot], (double)v[q].x);
           atomicAdd(&s_sum1[slot], (double)v[q].y);
           atomicAdd(&s_sum2[slot], (double)v[q].z);
+          if (var) {
+            const double y = luma64(v[q].x, v[q].y, v[q].z);
+            atomicAdd(&s_sumq[slot], y * y);
+          }
         }
       }
       if (results) {
@@ -698,6 +708,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     uint32_t cnt[kWb];
     Slot old[kWb];
     Acc acc_old[kWb];
+    float var_old[kWb];  // fused: the variance; else the bits of nothing
+    double q_old[kWb];   // not fused: the pending squared-luminance sum
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
       const uint32_t s = s0 + j * kMergeThreads + tid;
@@ -710,6 +722,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       const uint64_t src = base + (cnt[j] ? s0 + j * kMergeThreads + tid : 0u);
       old[j] = tv.slots[src];
       if (!kFused) acc_old[j] = tv.acc[src];
+      if (var) {
+        if (kFused)
+          var_old[j] = tv.var[src];
+        else
+          q_old[j] = tv.acc_q[src];
+      }
     }
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
@@ -729,6 +747,11 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         for (int ch = 0; ch < 3; ++ch) {
           const float m = means[ch];
           out[ch] = alpha == 1.0f ? m : (1.0f - alpha) * L[ch] + alpha * m;
+        }
+        if (var) {
+          double m, s2;
+          frame_moments(s_sum0[s], s_sum1[s], s_sum2[s], s_sumq[s], cd, m, s2);
+          tv.var[g] = blend_variance(var_old[j], alpha, luma32(L[0], L[1], L[2]), m, s2);
         }
         uint32_t enc[4], pad;
         encode_state(bp.dtype, out[0], out[1], out[2], enc, pad, sat);
@@ -758,6 +781,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         a.s[1] += (float)s_sum1[s];
         a.s[2] += (float)s_sum2[s];
         tv.acc[g] = a;
+        if (var) tv.acc_q[g] = q_old[j] + s_sumq[s];
         if (old[j].key != k) {
           tv.slots[g].key = k;
           tv.keys[g] = k;
@@ -924,7 +948,9 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
   return hist > stage ? hist : stage;
 }
 
-static size_t merge_lds(uint32_t part_log2) { return (size_t)(1u << part_log2) * (8 + 4 + 24); }
+static size_t merge_lds(const TableView& tv) {
+  return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + (tv.var ? 8 : 0));
+}
 
 // Raise a kernel's dynamic-LDS limit only as far as the launch needs (and
 // only when it exceeds the default 64 KiB).  The limit belongs to the
@@ -1004,7 +1030,7 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
   if (!partition_ok(tv, pv, n)) return hipErrorInvalidValue;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
-  const size_t shm = merge_lds(tv.part_log2);
+  const size_t shm = merge_lds(tv);
   static LdsLimit lim_f, lim_p;
   hipError_t e = fuse ? lds_limit(reinterpret_cast<const void*>(&k_merge<true>), shm, &lim_f)
                       : lds_limit(reinterpret_cast<const void*>(&k_merge<false>), shm, &lim_p);
@@ -1193,7 +1219,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
         S.ntrans != (S.pv.runs_t ? transpose_blocks(S.ntiles, 1u << (S.tv.log2_slots - S.tv.part_log2)) : 0u))
       return hipErrorInvalidValue;
     const uint32_t P = 1u << (S.tv.log2_slots - S.tv.part_log2);
-    const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv.part_log2);
+    const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv);
     lds_b = lb > lds_b ? lb : lds_b;
     lds_m = lm > lds_m ? lm : lds_m;
     if ((S.fused_query != 0) != (S.pv.perm != nullptr)) return hipErrorInvalidValue;

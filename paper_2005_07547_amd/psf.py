@@ -23,6 +23,7 @@ PSF_INSERT_AUTO, PSF_INSERT_DIRECT, PSF_INSERT_PARTITIONED = 0, 1, 2
 PSF_FLAG_PROBE_STATS = 1
 PSF_FLAG_TIMING = 2
 PSF_FLAG_TRANSPOSE_RUNS = 4
+PSF_FLAG_TRACK_VARIANCE = 8
 PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 PSF_PRIM_QUAD, PSF_PRIM_SPHERE = 0, 1
@@ -138,6 +139,7 @@ EXPORTS = [
     ("psf_export_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_export_cells_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_export_sh_cells", ctypes.c_int, [_vp, _vp, _vp, _vp, _u64, _P(_u64), _vp]),
+    ("psf_export_variance", ctypes.c_int, [_vp, _vp, _vp, _u64, _P(_u64), _vp]),
     ("psf_batch_create", ctypes.c_int, [_u32, _P(_vp)]),
     ("psf_batch_destroy", ctypes.c_int, [_vp]),
     ("psf_iterate_batch", ctypes.c_int, [_vp, _P(psf_session), _u32, _vp]),
@@ -369,6 +371,9 @@ class Table:
         return {self._lib.psf_kernel_name(k).decode(): (int(launches[k]), float(ms[k]))
                 for k in range(PSF_K_COUNT) if launches[k]}
 
+    def export_variance(self):
+        return export_variance(self)
+
     def export(self, noalloc: bool = False):
         """Occupied cells as numpy arrays: keys (uint64), n_new, c_old (uint32
         counts; float32 weight sums for a weighted table), L (3 x C).
@@ -411,6 +416,22 @@ def export_sh(t):
     if t.cfg.weighted:
         c_old = c_old.view(np.float32)
     return {"keys": keys[:c][order], "c_old": c_old[:c][order], "coeff": coeff[:, :c][:, order]}
+
+
+def export_variance(t):
+    """Occupied cells of a table created with PSF_FLAG_TRACK_VARIANCE: keys
+    (uint64) and each cell's luminance variance (float32), sorted by key."""
+    import numpy as np
+    st = t.stats()
+    cap = max(1, int(st["occupied"]))
+    keys = np.zeros(cap, dtype=np.uint64)
+    var = np.zeros(cap, dtype=np.float32)
+    count = ctypes.c_uint64()
+    _check(t._lib.psf_export_variance(t.handle, keys.ctypes.data, var.ctypes.data, cap, ctypes.byref(count),
+                                      current_stream()))
+    c = int(count.value)
+    order = np.argsort(keys[:c], kind="stable")
+    return keys[:c][order], var[:c][order]
 
 
 def estimate(t_oe, t_fli, a: dict, mode: int, param: float, out=None, applied=None):
