@@ -433,11 +433,14 @@ def form_weighted(torch, psf, W, iters=16):
         rec["weight"] = W.mis_weights(n, seed=40 + i, excluded=0.1)
         frames.append(_dev(rec, torch))
     plain = [{k: v for k, v in f.items() if k != "weight"} for f in frames]
+    # the weighted table takes its own default partition width (its merge
+    # holds a binary64 weight sum per slot in LDS as well)
+    pw = dict(tuned(wl["name"]), part_log2=0)
     res = {"workload": wl["name"], "records_per_iteration": n, "params": tuned(wl["name"]),
-           "weights": "balance heuristic of two lognormal(0, 1) densities, 10% zero"}
+           "params_weighted": pw, "weights": "balance heuristic of two lognormal(0, 1) densities, 10% zero"}
     for name, weighted, fr in (("weighted", 1, frames), ("unweighted", 0, plain)):
-        t = psf.Table(**dict(with_params(wl["table"], tuned(wl["name"]), psf.PSF_FLAG_TIMING),
-                             max_batch=n, weighted=weighted))
+        p = pw if weighted else tuned(wl["name"])
+        t = psf.Table(**dict(with_params(wl["table"], p, psf.PSF_FLAG_TIMING), max_batch=n, weighted=weighted))
         o = torch.empty((3, n), dtype=torch.float32, device="cuda")
         f = torch.empty(n, dtype=torch.uint8, device="cuda")
         for i in range(4):

@@ -173,10 +173,12 @@ typedef struct psf_config {
   int32_t insert_mode;       /* PSF_INSERT_* */
   uint32_t part_log2;        /* partitioned insert: log2 slots per partition
                                 (0 = default: 11, or 12 for tables of 2^25
-                                slots; else 8..12; at most 11 with
-                                PSF_FLAG_TRACK_VARIANCE).  A table of more
-                                than 8192 partitions takes the direct
-                                strategy. */
+                                slots; else 8..12.  With
+                                PSF_FLAG_TRACK_VARIANCE or weighted = 1:
+                                default 10, or 11 for tables of 2^24
+                                slots; at most 11).
+                                A table of more than 8192 partitions takes
+                                the direct strategy. */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M, at most 2^31); larger
                                 inserts are split */
@@ -191,7 +193,12 @@ typedef struct psf_config {
                                 a cell's counter is the binary32 sum of the
                                 weights that fell on it and its sample mean
                                 the weighted mean; Eq. 11 takes the weighted
-                                counters. */
+                                counters.  The partitioned insert sums a
+                                frame's weights in binary64 and rounds the
+                                sum once (the same bits on every run); the
+                                direct insert adds them with binary32
+                                atomics (like its value sums, the result
+                                depends on their order). */
   uint32_t payload;          /* PSF_PAYLOAD_RGB: the approximant is an RGB
                                 triple per cell.  PSF_PAYLOAD_SH2_YCOCG:
                                 luminance as two spherical-harmonic bands

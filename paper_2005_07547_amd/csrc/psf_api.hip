@@ -144,8 +144,8 @@ bool validate(const psf_config* c, std::string* why) {
     return bad("state_dtype must be F32, F16, BF16, F16_EF or BF16_EF");
   if (c->insert_mode < 0 || c->insert_mode > 2) return bad("insert_mode must be AUTO, DIRECT or PARTITIONED");
   if (c->part_log2 != 0 && (c->part_log2 < 8 || c->part_log2 > 12)) return bad("part_log2 must be 0 or in [8, 12]");
-  if ((c->flags & PSF_FLAG_TRACK_VARIANCE) && c->part_log2 == 12)
-    return bad("part_log2 must be at most 11 in a table that keeps the variance");
+  if (((c->flags & PSF_FLAG_TRACK_VARIANCE) || c->weighted) && c->part_log2 == 12)
+    return bad("part_log2 must be at most 11 in a weighted table or one that keeps the variance");
   if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS |
                              PSF_FLAG_TRACK_VARIANCE))
     return bad("unknown flags");
@@ -171,10 +171,12 @@ Layout layout_of(const psf_config& c) {
   const uint64_t S = 1ull << c.log2_slots;
   // default partition width: 2^11 slots, wider for tables that would
   // otherwise exceed the binning pass's partition count
-  // (at most 2^11 with the variance's further LDS sum: 2^12 slots of 44
-  // bytes exceed a workgroup's LDS)
-  const uint32_t widest = (c.flags & PSF_FLAG_TRACK_VARIANCE) ? 11u : 12u;
-  uint32_t def = kDefaultPartLog2;
+  // (with the further LDS sum of the variance or of the weights, 2^10 by
+  // default, which keeps two blocks per CU, and at most 2^11: 2^12 slots of
+  // 44 bytes exceed a workgroup's LDS)
+  const bool extra = (c.flags & PSF_FLAG_TRACK_VARIANCE) || c.weighted;
+  const uint32_t widest = extra ? 11u : 12u;
+  uint32_t def = extra ? kDefaultPartLog2 - 1 : kDefaultPartLog2;
   while (def < widest && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kMaxPartitions) ++def;
   L.part_log2 = c.part_log2 ? c.part_log2 : def;
   if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;

@@ -444,10 +444,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
                                            const BlendParams& bp, uint32_t blk, bool results) {
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
   // than f32 ones on gfx950 and exact enough to make the sum order
-  // immaterial), then, in a table that keeps the luminance variance,
-  // sumq[B] (the squared luminances; every entry is one record there).
-  // After the blend the sums hold the cells' new values.  In a weighted
-  // table cnt holds binary32 weight sums.
+  // immaterial), then, in a table that keeps the luminance variance or has
+  // weighted counters, sumx[B]: the squared luminances, or the weights
+  // (binary64 like the value sums, rounded once to binary32 at the
+  // write-back, so the counters do not depend on the order of the atomics;
+  // cnt then only marks the slots touched).  Every entry is one record in
+  // such tables.  After the blend the sums hold the cells' new values.
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_touched, s_sat;
   __shared__ uint32_t s_hist[16];
@@ -464,7 +466,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   double* s_sum0 = reinterpret_cast<double*>(s_cnt + B);  // B >= 256: 8-byte aligned
   double* s_sum1 = s_sum0 + B;
   double* s_sum2 = s_sum1 + B;
-  double* s_sumq = s_sum2 + B;  // only with tv.var
+  double* s_sumx = s_sum2 + B;  // only with tv.var or wtd
   const bool var = tv.var != nullptr;
   const uint32_t tile = pv.tile;
   if (!kFused) results = false;
@@ -614,7 +616,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       s_key[s] = kk[j];
       s_cnt[s] = 0;
       s_sum0[s] = s_sum1[s] = s_sum2[s] = 0.0;
-      if (var) s_sumq[s] = 0.0;
+      if (var || wtd) s_sumx[s] = 0.0;
     }
   }
   if (tid == 0) s_dropped = s_touched = s_sat = 0;
@@ -656,16 +658,18 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           atomicAdd(&s_dropped, recs);
         } else {
           if (stats) atomicAdd(&s_hist[i < 15 ? i : 15], recs);
-          if (wtd)
-            atomicAdd(reinterpret_cast<float*>(&s_cnt[slot]), v[q].w);
-          else
+          if (wtd) {
+            atomicAdd(&s_sumx[slot], (double)v[q].w);
+            s_cnt[slot] = 1u;
+          } else {
             atomicAdd(&s_cnt[slot], (uint32_t)v[q].w);
+          }
           atomicAdd(&s_sum0[slot], (double)v[q].x);
           atomicAdd(&s_sum1[slot], (double)v[q].y);
           atomicAdd(&s_sum2[slot], (double)v[q].z);
           if (var) {
             const double y = luma64(v[q].x, v[q].y, v[q].z);
-            atomicAdd(&s_sumq[slot], y * y);
+            atomicAdd(&s_sumx[slot], y * y);
           }
         }
       }
@@ -734,7 +738,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       if (cnt[j] == 0) continue;
       const uint32_t s = s0 + j * kMergeThreads + tid;
       const uint64_t g = base + s;
-      const uint32_t c = cnt[j];
+      // the frame's counter word (a weighted table's weight sum rounds once)
+      const uint32_t c = wtd ? __float_as_uint((float)s_sumx[s]) : cnt[j];
       const unsigned long long k = s_key[s];
       if (kFused) {
         const float alpha = blend_alpha(bp, c, old[j].c_old, wtd);
@@ -750,7 +755,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         }
         if (var) {
           double m, s2;
-          frame_moments(s_sum0[s], s_sum1[s], s_sum2[s], s_sumq[s], cd, m, s2);
+          frame_moments(s_sum0[s], s_sum1[s], s_sum2[s], s_sumx[s], cd, m, s2);
           tv.var[g] = blend_variance(var_old[j], alpha, luma32(L[0], L[1], L[2]), m, s2);
         }
         uint32_t enc[4], pad;
@@ -781,7 +786,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         a.s[1] += (float)s_sum1[s];
         a.s[2] += (float)s_sum2[s];
         tv.acc[g] = a;
-        if (var) tv.acc_q[g] = q_old[j] + s_sumq[s];
+        if (var) tv.acc_q[g] = q_old[j] + s_sumx[s];
         if (old[j].key != k) {
           tv.slots[g].key = k;
           tv.keys[g] = k;
@@ -949,7 +954,7 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
 }
 
 static size_t merge_lds(const TableView& tv) {
-  return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + (tv.var ? 8 : 0));
+  return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + ((tv.var || weighted(tv)) ? 8 : 0));
 }
 
 // Raise a kernel's dynamic-LDS limit only as far as the launch needs (and

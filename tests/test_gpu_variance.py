@@ -191,6 +191,9 @@ def test_variance_argument_checks(env):
     with pytest.raises(psf.PsfError) as e:
         psf.Table(log2_slots=14, flags=psf.PSF_FLAG_TRACK_VARIANCE, part_log2=12)
     assert e.value.status == psf.PSF_INVALID_ARGUMENT
+    with pytest.raises(psf.PsfError) as e:
+        psf.Table(log2_slots=14, weighted=1, part_log2=12)
+    assert e.value.status == psf.PSF_INVALID_ARGUMENT
     t = psf.Table(log2_slots=12)
     with pytest.raises(psf.PsfError) as e:
         t.export_variance()

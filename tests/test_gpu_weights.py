@@ -5,7 +5,9 @@ batched form, and the tables' argument checks.
 
 Counters are binary32 weight sums on the GPU (binary64 in the oracle), so
 they are compared to a relative tolerance instead of bit for bit; keys and
-found flags stay bit-exact."""
+found flags stay bit-exact.  The partitioned insert rounds each frame's
+binary64 weight sum once, which is checked exactly, with run-to-run
+reproducibility."""
 import numpy as np
 import pytest
 
@@ -118,6 +120,44 @@ def test_weighted_plain_workload_first_iterations(env, fused):
         assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32, it
         del d, out, found
     _compare(t, orc, "plain")
+
+
+def test_partitioned_weight_sums_round_once_and_reproduce(env):
+    """The partitioned insert sums a frame's weights in binary64 and rounds
+    once: a first frame's counters are the oracle's binary64 sums rounded
+    to binary32, and two runs of the full-size workload agree bit for bit
+    (counters and approximant), whatever the order of the LDS atomics."""
+    import oracle
+    from synth import workloads as W
+    torch, psf = env
+    wl, rec = _tiny(0)
+    rec["weight"] = _weights(len(rec["px"]), 0, bad=False)
+    cfg = dict(wl["table"], weighted=1)
+    orc = oracle.Oracle(**cfg)
+    orc.insert(rec)
+    t = psf.Table(**cfg, insert_mode=2)
+    t.insert(to_device(rec))
+    torch.cuda.synchronize()
+    g, o = t.export(), orc.export()
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.array_equal(g["n_new"], o["n_new"].astype(np.float32))
+
+    wl = W.plain()
+    sc = W.make_scene(wl)
+    cfg = dict(wl["table"], weighted=1)
+    runs = [psf.Table(**cfg, insert_mode=2), psf.Table(**cfg, insert_mode=2)]
+    for it in range(3):
+        rec = dict(sc.generate(wl["gen"], it))
+        rec["weight"] = _weights(len(rec["px"]), it, bad=False)
+        d = to_device(rec)
+        for t in runs:
+            t.iterate(d)
+        del d
+    torch.cuda.synchronize()
+    a, b = runs[0].export(), runs[1].export()
+    assert np.array_equal(a["keys"], b["keys"])
+    assert np.array_equal(a["c_old"].view(np.uint32), b["c_old"].view(np.uint32))
+    assert np.array_equal(a["L"].view(np.uint32), b["L"].view(np.uint32))
 
 
 @pytest.mark.parametrize("insert_mode", [1, 2])
