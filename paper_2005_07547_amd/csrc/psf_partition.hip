@@ -450,8 +450,9 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   // write-back, so the counters do not depend on the order of the atomics;
   // cnt then only marks the slots touched).  Every entry is one record in
   // such tables.  After the blend the sums hold the cells' new values.
+  // Last, list[B] (16-bit): the touched slots, gathered for the write-back.
   extern __shared__ unsigned long long s_dyn[];
-  __shared__ uint32_t s_dropped, s_touched, s_sat;
+  __shared__ uint32_t s_dropped, s_nlist, s_sat;
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   constexpr uint32_t kWaves = kMergeThreads / 64;
@@ -468,6 +469,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   double* s_sum2 = s_sum1 + B;
   double* s_sumx = s_sum2 + B;  // only with tv.var or wtd
   const bool var = tv.var != nullptr;
+  // the touched slots' indices (B entries), after the sums
+  uint16_t* s_list = reinterpret_cast<uint16_t*>(s_sumx + ((var || wtd) ? B : 0u));
   const uint32_t tile = pv.tile;
   if (!kFused) results = false;
 
@@ -619,7 +622,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       if (var || wtd) s_sumx[s] = 0.0;
     }
   }
-  if (tid == 0) s_dropped = s_touched = s_sat = 0;
+  if (tid == 0) s_dropped = s_nlist = s_sat = 0;
   if (tid < 16) s_hist[tid] = 0;
   __syncthreads();
 
@@ -703,27 +706,40 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   }
   __syncthreads();
 
-  // write the partition back; the old slots of a group are loaded together
-  // so the group costs one memory round trip
+  // List the touched slots (about one in eight, scattered), so that the
+  // write-back runs on full waves: each thread then blends at most kWb
+  // cells, whose old slots are loaded together (one memory round trip).
+  for (uint32_t s0 = 0; s0 < B; s0 += kMergeThreads) {
+    const uint32_t s = s0 + tid;
+    const bool hit = s < B && s_cnt[s] != 0u;
+    const unsigned long long m = __ballot(hit);
+    uint32_t at = 0;
+    if (lane == 0 && m) at = atomicAdd(&s_nlist, (uint32_t)__popcll(m));
+    at = (uint32_t)__shfl((int)at, 0);
+    if (hit)
+      s_list[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+          (uint16_t)s;
+  }
+  __syncthreads();
+  const uint32_t n_touched = s_nlist;
   bool sat = false;
-  uint32_t touched = 0;
-  constexpr uint32_t kWb = 4;
-  for (uint32_t s0 = 0; s0 < B; s0 += kWb * kMergeThreads) {
-    uint32_t cnt[kWb];
+  constexpr uint32_t kWb = 2;
+  for (uint32_t i0 = 0; i0 < n_touched; i0 += kWb * kMergeThreads) {
+    uint32_t sl[kWb];
     Slot old[kWb];
     Acc acc_old[kWb];
-    float var_old[kWb];  // fused: the variance; else the bits of nothing
+    float var_old[kWb];  // fused: the variance
     double q_old[kWb];   // not fused: the pending squared-luminance sum
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
-      const uint32_t s = s0 + j * kMergeThreads + tid;
-      cnt[j] = s < B ? s_cnt[s] : 0u;
+      const uint32_t i = i0 + j * kMergeThreads + tid;
+      sl[j] = i < n_touched ? (uint32_t)s_list[i] : ~0u;
     }
-    // untouched slots all read the partition's first slot (one shared line)
-    // so the group's loads carry no branches and overlap
+    // absent entries read the partition's first slot, so that the group's
+    // loads carry no branches and overlap
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
-      const uint64_t src = base + (cnt[j] ? s0 + j * kMergeThreads + tid : 0u);
+      const uint64_t src = base + (sl[j] != ~0u ? sl[j] : 0u);
       old[j] = tv.slots[src];
       if (!kFused) acc_old[j] = tv.acc[src];
       if (var) {
@@ -735,11 +751,11 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     }
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
-      if (cnt[j] == 0) continue;
-      const uint32_t s = s0 + j * kMergeThreads + tid;
+      if (sl[j] == ~0u) continue;
+      const uint32_t s = sl[j];
       const uint64_t g = base + s;
       // the frame's counter word (a weighted table's weight sum rounds once)
-      const uint32_t c = wtd ? __float_as_uint((float)s_sumx[s]) : cnt[j];
+      const uint32_t c = wtd ? __float_as_uint((float)s_sumx[s]) : s_cnt[s];
       const unsigned long long k = s_key[s];
       if (kFused) {
         const float alpha = blend_alpha(bp, c, old[j].c_old, wtd);
@@ -770,7 +786,6 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         nw.L[3] = enc[3];
         tv.slots[g] = nw;
         if (old[j].key != k) tv.keys[g] = k;
-        ++touched;
         if (results) {
           // what a lookup of the cell returns from now on
           float v[3];
@@ -794,11 +809,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
       }
     }
   }
-  if (kFused) {
-    for (int off = 32; off > 0; off >>= 1) touched += __shfl_xor(touched, off);
-    if (__lane_id() == 0 && touched) atomicAdd(&s_touched, touched);
-    if (sat) atomicAdd(&s_sat, 1u);
-  }
+  if (kFused && sat) atomicAdd(&s_sat, 1u);
   __syncthreads();
 
   if (results) {
@@ -857,8 +868,8 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     if (kFused) {
       if (s_sat) atomicAdd(&tv.stats->saturated, (unsigned long long)s_sat);
       BlockTouch* bt = &tv.touch[blk];
-      bt->last = s_touched;
-      bt->total += s_touched;
+      bt->last = n_touched;
+      bt->total += n_touched;
     }
   }
   if (stats && tid < 16 && s_hist[tid])
@@ -954,7 +965,7 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
 }
 
 static size_t merge_lds(const TableView& tv) {
-  return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + ((tv.var || weighted(tv)) ? 8 : 0));
+  return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + ((tv.var || weighted(tv)) ? 8 : 0) + 2);
 }
 
 // Raise a kernel's dynamic-LDS limit only as far as the launch needs (and
