@@ -179,6 +179,32 @@ def test_plain_workload_variance_sampled(env):
     assert t.stats()["dropped"] == 0
 
 
+@pytest.mark.parametrize("how", ["counters", "clear", "region"])
+def test_variance_after_resets(env, how):
+    """A counter reset (global or by region) restarts the variance at the
+    next blend; clearing the table forgets it."""
+    import oracle
+    torch, psf = env
+    wl, frames = _tiny_frames(6, 0)
+    t = psf.Table(**dict(wl["table"], flags=psf.PSF_FLAG_TRACK_VARIANCE))
+    orc = oracle.Oracle(**wl["table"])
+    for i, rec in enumerate(frames):
+        if i == 3:
+            if how == "region":
+                t.reset_region((0.0, 0.0, 0.0), (0.5, 1.0, 1.0))
+                orc.reset_region((0.0, 0.0, 0.0), (0.5, 1.0, 1.0))
+            else:
+                what = psf.PSF_RESET_COUNTERS if how == "counters" else psf.PSF_RESET_CLEAR
+                t.reset(what)
+                orc.reset(what)
+        t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+    torch.cuda.synchronize()
+    compare_cells(t.export(), orc.export(), RTOL, how)
+    _compare_variance(t, orc, RTOL, how)
+
+
 def test_variance_argument_checks(env):
     torch, psf = env
     with pytest.raises(psf.PsfError) as e:
