@@ -179,6 +179,31 @@ def test_plain_workload_variance_sampled(env):
     assert t.stats()["dropped"] == 0
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_variance_ignores_rejected_records(env, mode):
+    """Records with a non-finite value or position are skipped: they add
+    nothing to a cell's squared-luminance sum (the partitioned path stages
+    them for lookup only)."""
+    import oracle
+    torch, psf = env
+    wl, frames = _tiny_frames(3, 0)
+    t = psf.Table(**dict(wl["table"], insert_mode=mode, flags=psf.PSF_FLAG_TRACK_VARIANCE))
+    orc = oracle.Oracle(**wl["table"])
+    for i, rec in enumerate(frames):
+        rec = {k: (None if v is None else v.copy()) for k, v in rec.items()}
+        n = len(rec["px"])
+        rec["g"][i::97] = np.nan
+        rec["r"][i + 5::131] = np.inf
+        rec["px"][i + 11::173] = np.nan
+        t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+    torch.cuda.synchronize()
+    assert t.stats()["skipped"] == orc.counters()["skipped"]
+    compare_cells(t.export(), orc.export(), RTOL, f"mode {mode}")
+    _compare_variance(t, orc, RTOL, f"mode {mode}")
+
+
 @pytest.mark.parametrize("how", ["counters", "clear", "region"])
 def test_variance_after_resets(env, how):
     """A counter reset (global or by region) restarts the variance at the
