@@ -121,7 +121,7 @@ enum {
  * gives frame j's mean in the approximant).  Memory: 12 more bytes per slot.
  * The partitioned insert stages every record as its own entry in such a
  * table (no pre-merge of neighbouring duplicates) and its merge pass holds
- * a further binary64 sum per slot in LDS (44 instead of 36 bytes). */
+ * a further binary64 sum per slot in LDS (46 instead of 38 bytes). */
 
 /* Kernel kinds reported by psf_kernel_times. */
 enum {

@@ -173,7 +173,7 @@ Layout layout_of(const psf_config& c) {
   // otherwise exceed the binning pass's partition count
   // (with the further LDS sum of the variance or of the weights, 2^10 by
   // default, which keeps two blocks per CU, and at most 2^11: 2^12 slots of
-  // 44 bytes exceed a workgroup's LDS)
+  // 46 bytes exceed a workgroup's LDS)
   const bool extra = (c.flags & PSF_FLAG_TRACK_VARIANCE) || c.weighted;
   const uint32_t widest = extra ? 11u : 12u;
   uint32_t def = extra ? kDefaultPartLog2 - 1 : kDefaultPartLog2;
