@@ -439,7 +439,7 @@ __device__ __forceinline__ uint32_t wave_upper_bound(uint32_t excl, uint32_t e) 
 // mode only), every staged entry of the partition is overwritten with the
 // value its cell holds after the blend (kDroppedBits in place of red when
 // its key found no slot).
-template <bool kFused>
+template <bool kFused, int kThreads = kMergeThreads>
 __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& pv, uint32_t ntiles,
                                            const BlendParams& bp, uint32_t blk, bool results) {
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
@@ -455,7 +455,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   __shared__ uint32_t s_dropped, s_nlist, s_sat;
   __shared__ uint32_t s_hist[16];
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-  constexpr uint32_t kWaves = kMergeThreads / 64;
+  constexpr uint32_t kWaves = kThreads / 64;
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t B = 1u << tv.part_log2;
   const uint32_t p = xcd_partition(blk, P);
@@ -591,11 +591,11 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
 
   // keys first, then the first runs, then the wave's first batch of entries:
   // all in flight together, before the key table is built
-  constexpr uint32_t kKeysPerThread = (1u << kMaxPartLog2) / kMergeThreads;
+  constexpr uint32_t kKeysPerThread = (1u << kMaxPartLog2) / kThreads;
   unsigned long long kk[kKeysPerThread];
 #pragma unroll
   for (uint32_t j = 0; j < kKeysPerThread; ++j) {
-    const uint32_t s = tid + j * kMergeThreads;
+    const uint32_t s = tid + j * kThreads;
     kk[j] = s < B ? tv.keys[base + s] : kEmpty;
   }
   Chunk ch0{};
@@ -614,7 +614,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   }
 #pragma unroll
   for (uint32_t j = 0; j < kKeysPerThread; ++j) {
-    const uint32_t s = tid + j * kMergeThreads;
+    const uint32_t s = tid + j * kThreads;
     if (s < B) {
       s_key[s] = kk[j];
       s_cnt[s] = 0;
@@ -709,7 +709,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   // List the touched slots (about one in eight, scattered), so that the
   // write-back runs on full waves: each thread then blends at most kWb
   // cells, whose old slots are loaded together (one memory round trip).
-  for (uint32_t s0 = 0; s0 < B; s0 += kMergeThreads) {
+  for (uint32_t s0 = 0; s0 < B; s0 += kThreads) {
     const uint32_t s = s0 + tid;
     const bool hit = s < B && s_cnt[s] != 0u;
     const unsigned long long m = __ballot(hit);
@@ -724,7 +724,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   const uint32_t n_touched = s_nlist;
   bool sat = false;
   constexpr uint32_t kWb = 2;
-  for (uint32_t i0 = 0; i0 < n_touched; i0 += kWb * kMergeThreads) {
+  for (uint32_t i0 = 0; i0 < n_touched; i0 += kWb * kThreads) {
     uint32_t sl[kWb];
     Slot old[kWb];
     Acc acc_old[kWb];
@@ -732,7 +732,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     double q_old[kWb];   // not fused: the pending squared-luminance sum
 #pragma unroll
     for (uint32_t j = 0; j < kWb; ++j) {
-      const uint32_t i = i0 + j * kMergeThreads + tid;
+      const uint32_t i = i0 + j * kThreads + tid;
       sl[j] = i < n_touched ? (uint32_t)s_list[i] : ~0u;
     }
     // absent entries read the partition's first slot, so that the group's
@@ -876,10 +876,12 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     atomicAdd(&tv.stats->probe_hist[tid], (unsigned long long)s_hist[tid]);
 }
 
-template <bool kFused>
-__global__ void __launch_bounds__(kMergeThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles,
-                                                         BlendParams bp, int32_t results) {
-  merge_body<kFused>(tv, pv, ntiles, bp, blockIdx.x, results != 0);
+// 512 threads per partition block, 1024 for 4096-slot partitions (one block
+// per CU either way the LDS allows: 16 waves per CU).
+template <bool kFused, int kThreads>
+__global__ void __launch_bounds__(kThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles, BlendParams bp,
+                                                    int32_t results) {
+  merge_body<kFused, kThreads>(tv, pv, ntiles, bp, blockIdx.x, results != 0);
 }
 
 // ------------------------------------------------------------------ unstage
@@ -1047,16 +1049,25 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
   const uint32_t P = 1u << (tv.log2_slots - tv.part_log2);
   const uint32_t ntiles = (uint32_t)((n + pv.tile - 1) / pv.tile);
   const size_t shm = merge_lds(tv);
-  static LdsLimit lim_f, lim_p;
-  hipError_t e = fuse ? lds_limit(reinterpret_cast<const void*>(&k_merge<true>), shm, &lim_f)
-                      : lds_limit(reinterpret_cast<const void*>(&k_merge<false>), shm, &lim_p);
-  if (e != hipSuccess) return e;
   // staged lookup-only entries exist exactly when the bin pass wrote perm
   if (results != (pv.perm != nullptr) || (results && !fuse)) return hipErrorInvalidValue;
-  if (fuse)
-    k_merge<true><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse, results ? 1 : 0);
+  static LdsLimit lim[4];
+  const bool wide = tv.part_log2 >= kMaxPartLog2;
+  const void* fn = fuse ? (wide ? reinterpret_cast<const void*>(&k_merge<true, 1024>)
+                                : reinterpret_cast<const void*>(&k_merge<true, kMergeThreads>))
+                        : (wide ? reinterpret_cast<const void*>(&k_merge<false, 1024>)
+                                : reinterpret_cast<const void*>(&k_merge<false, kMergeThreads>));
+  hipError_t e = lds_limit(fn, shm, &lim[(fuse ? 2 : 0) + (wide ? 1 : 0)]);
+  if (e != hipSuccess) return e;
+  const int32_t res = results ? 1 : 0;
+  if (fuse && wide)
+    k_merge<true, 1024><<<P, 1024, shm, s>>>(tv, pv, ntiles, *fuse, res);
+  else if (fuse)
+    k_merge<true, kMergeThreads><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, *fuse, res);
+  else if (wide)
+    k_merge<false, 1024><<<P, 1024, shm, s>>>(tv, pv, ntiles, BlendParams{}, 0);
   else
-    k_merge<false><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, BlendParams{}, 0);
+    k_merge<false, kMergeThreads><<<P, kMergeThreads, shm, s>>>(tv, pv, ntiles, BlendParams{}, 0);
   return hipGetLastError();
 }
 
