@@ -1167,15 +1167,17 @@ k_bin_batch(const BatchSession* ss, const uint32_t* bg, uint32_t k) {
   bin_session<kPer, 0, kX & kXFootprint>(S, local);
 }
 
-__global__ void __launch_bounds__(kMergeThreads) k_merge_batch(const BatchSession* ss, const uint32_t* bg,
-                                                                uint32_t k) {
+// 1024 threads per block when the widest session has 4096-slot partitions
+// (its LDS allows one block per CU), else 512.
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_merge_batch(const BatchSession* ss, const uint32_t* bg, uint32_t k) {
   const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
   const uint32_t local = blockIdx.x - S.part_begin;
   if (local >= S.nparts) return;
   const TableView tv = S.tv;
   const PartView pv = S.pv;
   const BlendParams bp = S.bp;
-  merge_body<true>(tv, pv, S.ntiles, bp, local, S.fused_query != 0);
+  merge_body<true, kThreads>(tv, pv, S.ntiles, bp, local, S.fused_query != 0);
 }
 
 // A session whose queries are its records takes one unstage block per tile;
@@ -1233,6 +1235,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
   if (k > stride) return hipErrorInvalidValue;
   uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   size_t lds_b = 0, lds_m = 0, lds_q = 0;
+  uint32_t widest = 0;  // largest part_log2 of the sessions
   uint32_t x = 0;  // what any session's records carry
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
@@ -1249,6 +1252,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
     const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv);
     lds_b = lb > lds_b ? lb : lds_b;
     lds_m = lm > lds_m ? lm : lds_m;
+    widest = S.tv.part_log2 > widest ? S.tv.part_log2 : widest;
     if ((S.fused_query != 0) != (S.pv.perm != nullptr)) return hipErrorInvalidValue;
     if (S.fused_query) {
       if (S.nq != S.n || S.nqblk != S.ntiles) return hipErrorInvalidValue;
@@ -1262,7 +1266,8 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
     qblks += S.nqblk;
     trans += S.ntrans;
   }
-  static LdsLimit lim_m, lim_q;
+  static LdsLimit lim_m[2], lim_q;
+  const bool wide = widest >= kMaxPartLog2;
   const uint32_t* bg_tile = d_begins;
   const uint32_t* bg_part = d_begins + stride;
   const uint32_t* bg_qblk = d_begins + 2 * stride;
@@ -1271,13 +1276,17 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
                   : per == 12 ? launch_bin_batch_x<12>(x, d_ss, bg_tile, k, tiles, lds_b, s)
                               : launch_bin_batch_x<16>(x, d_ss, bg_tile, k, tiles, lds_b, s);
   if (e != hipSuccess) return e;
-  e = lds_limit(reinterpret_cast<const void*>(&k_merge_batch), lds_m, &lim_m);
+  e = wide ? lds_limit(reinterpret_cast<const void*>(&k_merge_batch<1024>), lds_m, &lim_m[1])
+           : lds_limit(reinterpret_cast<const void*>(&k_merge_batch<kMergeThreads>), lds_m, &lim_m[0]);
   if (e == hipSuccess) e = lds_limit(reinterpret_cast<const void*>(&k_query_batch), lds_q, &lim_q);
   if (e != hipSuccess) return e;
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (trans) k_transpose_batch<<<trans, kTransposeThreads, 0, s>>>(d_ss, bg_trans, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_merge_batch<<<parts, kMergeThreads, lds_m, s>>>(d_ss, bg_part, k);
+  if (wide)
+    k_merge_batch<1024><<<parts, 1024, lds_m, s>>>(d_ss, bg_part, k);
+  else
+    k_merge_batch<kMergeThreads><<<parts, kMergeThreads, lds_m, s>>>(d_ss, bg_part, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (qblks) k_query_batch<<<qblks, kQueryBlock, lds_q, s>>>(d_ss, bg_qblk, k);
   return hipGetLastError();

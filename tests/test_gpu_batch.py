@@ -35,16 +35,17 @@ def _frame(wl, sc, it):
     return sc.generate(wl["gen"], it)
 
 
-@pytest.mark.parametrize("transpose", [False, True])
-def test_batch_equals_alone_and_oracle(env, transpose):
+@pytest.mark.parametrize("transpose,part_log2", [(False, 0), (True, 0), (False, 12), (True, 12)])
+def test_batch_equals_alone_and_oracle(env, transpose, part_log2):
     import oracle
     torch, psf = env
     ss = _sessions()
     # transposing every session's run table covers the merge pass's other
-    # way of reading it; mixing flags covers sessions that differ in it
+    # way of reading it; mixing flags covers sessions that differ in it;
+    # 4096-slot partitions in every session take the 1024-thread merge
     fl = [psf.PSF_FLAG_TRANSPOSE_RUNS if transpose and i % 2 == 0 else 0 for i in range(len(ss))]
-    alone = [psf.Table(**wl["table"], flags=f) for (wl, _), f in zip(ss, fl)]
-    mixed = [psf.Table(**wl["table"], flags=f) for (wl, _), f in zip(ss, fl)]
+    alone = [psf.Table(**wl["table"], flags=f, part_log2=part_log2) for (wl, _), f in zip(ss, fl)]
+    mixed = [psf.Table(**wl["table"], flags=f, part_log2=part_log2) for (wl, _), f in zip(ss, fl)]
     orcs = [oracle.Oracle(**wl["table"]) for wl, _ in ss]
     batch = psf.Batch(16)
     for it in range(3):
@@ -195,16 +196,19 @@ def test_full_size_batched_sessions_sampled_cells(env):
     iterations.  A sample of each session's cells is tracked by the binary64
     oracle (key-sharded over the host threads): keys and counts bit-exact,
     FP32 state within 1e-5, and every record that falls in a sampled cell
-    gets the oracle's lookup from the fused answer pass."""
+    gets the oracle's lookup from the fused answer pass.  The tables take
+    the launch parameters the benchmark times (the autotuner's record)."""
     import os
     import oracle
+    from paper_2005_07547_amd import autotune
     from synth import workloads as W
     torch, psf = env
     wls = W.batched_sessions(16)
     scs = [W.make_scene(wl) for wl in wls]
     ns = [W.records_per_iteration(wl) for wl in wls]
     assert sum(ns) > 100_000_000
-    tables = [psf.Table(**dict(wl["table"], max_batch=n)) for wl, n in zip(wls, ns)]
+    params = autotune.best_params("batched-16")
+    tables = [psf.Table(**dict(wl["table"], max_batch=n, **params)) for wl, n in zip(wls, ns)]
     threads = min(16, os.cpu_count() or 1)
     orcs = [oracle.ShardedOracle(threads, **wl["table"]) for wl in wls]
     batch = psf.Batch(16)

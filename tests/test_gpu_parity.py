@@ -182,12 +182,13 @@ def test_plain_workload_sampled_cells_many_iterations(psf, torch_cuda):
     """Full-size plain workload in the launch configuration the benchmark
     times (fused partitioned iteration, 2^22 slots); the oracle tracks a
     sample of cells over every iteration."""
+    from paper_2005_07547_amd import autotune
     from synth import workloads as W
     wl = W.plain()
     iters = 8
     sc = W.make_scene(wl)
     orc = _oracle(wl["table"])
-    t = _table(psf, wl["table"])
+    t = _table(psf, wl["table"], **autotune.best_params(wl["name"]))
     first = sc.generate(wl["gen"], 0)
     keys0, _ = orc.keys(first)
     rng = np.random.default_rng(1)
