@@ -876,8 +876,9 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     atomicAdd(&tv.stats->probe_hist[tid], (unsigned long long)s_hist[tid]);
 }
 
-// 512 threads per partition block, 1024 for 4096-slot partitions (one block
-// per CU either way the LDS allows: 16 waves per CU).
+// 512 threads per partition block, 1024 where the partition's LDS allows
+// one block per CU (4096 slots, or 2048 with a fifth sum per slot): 16
+// waves per CU either way.
 template <bool kFused, int kThreads>
 __global__ void __launch_bounds__(kThreads) k_merge(TableView tv, PartView pv, uint32_t ntiles, BlendParams bp,
                                                     int32_t results) {
@@ -966,6 +967,10 @@ static size_t bin_lds(uint32_t P, uint32_t per) {
   return hist > stage ? hist : stage;
 }
 
+// A merge block whose LDS leaves room for no second block on a CU (160 KB)
+// takes 1024 threads, so that the CU still runs 16 waves.
+static bool merge_wide(size_t lds) { return lds > 80 * 1024; }
+
 static size_t merge_lds(const TableView& tv) {
   return (size_t)(1u << tv.part_log2) * (8 + 4 + 24 + ((tv.var || weighted(tv)) ? 8 : 0) + 2);
 }
@@ -1052,7 +1057,7 @@ hipError_t launch_merge(uint64_t n, const TableView& tv, const PartView& pv, con
   // staged lookup-only entries exist exactly when the bin pass wrote perm
   if (results != (pv.perm != nullptr) || (results && !fuse)) return hipErrorInvalidValue;
   static LdsLimit lim[4];
-  const bool wide = tv.part_log2 >= kMaxPartLog2;
+  const bool wide = merge_wide(shm);
   const void* fn = fuse ? (wide ? reinterpret_cast<const void*>(&k_merge<true, 1024>)
                                 : reinterpret_cast<const void*>(&k_merge<true, kMergeThreads>))
                         : (wide ? reinterpret_cast<const void*>(&k_merge<false, 1024>)
@@ -1167,8 +1172,8 @@ k_bin_batch(const BatchSession* ss, const uint32_t* bg, uint32_t k) {
   bin_session<kPer, 0, kX & kXFootprint>(S, local);
 }
 
-// 1024 threads per block when the widest session has 4096-slot partitions
-// (its LDS allows one block per CU), else 512.
+// 1024 threads per block when the widest session's partitions leave room
+// for one block per CU, else 512.
 template <int kThreads>
 __global__ void __launch_bounds__(kThreads) k_merge_batch(const BatchSession* ss, const uint32_t* bg, uint32_t k) {
   const BatchSession& S = ss[find_session(bg, k, blockIdx.x)];
@@ -1235,7 +1240,6 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
   if (k > stride) return hipErrorInvalidValue;
   uint32_t tiles = 0, parts = 0, qblks = 0, trans = 0;
   size_t lds_b = 0, lds_m = 0, lds_q = 0;
-  uint32_t widest = 0;  // largest part_log2 of the sessions
   uint32_t x = 0;  // what any session's records carry
   const uint32_t per = h_ss[0].pv.tile / kBinThreads;
   for (uint32_t i = 0; i < k; ++i) {
@@ -1252,7 +1256,6 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
     const size_t lb = bin_lds(P, per), lm = merge_lds(S.tv);
     lds_b = lb > lds_b ? lb : lds_b;
     lds_m = lm > lds_m ? lm : lds_m;
-    widest = S.tv.part_log2 > widest ? S.tv.part_log2 : widest;
     if ((S.fused_query != 0) != (S.pv.perm != nullptr)) return hipErrorInvalidValue;
     if (S.fused_query) {
       if (S.nq != S.n || S.nqblk != S.ntiles) return hipErrorInvalidValue;
@@ -1267,7 +1270,7 @@ hipError_t launch_batch(const BatchSession* d_ss, const uint32_t* d_begins, cons
     trans += S.ntrans;
   }
   static LdsLimit lim_m[2], lim_q;
-  const bool wide = widest >= kMaxPartLog2;
+  const bool wide = merge_wide(lds_m);
   const uint32_t* bg_tile = d_begins;
   const uint32_t* bg_part = d_begins + stride;
   const uint32_t* bg_qblk = d_begins + 2 * stride;
