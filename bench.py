@@ -76,6 +76,56 @@ def measured_traffic(workload: str, kernel: str, key: str = "bytes"):
     return int(hits[0][key]) if len(hits) == 1 and key in hits[0] else None
 
 
+def device_rates(torch, dev, reps=5):
+    """Rates of the memory operations the hash path is made of, measured with
+    HIP events over torch's own kernels: a streaming 1 GiB copy (bytes moved
+    per second), gathers of 2^24 random 16-byte rows (torch.take of each
+    row's four words; rows per second) and
+    2^24 random binary32 and u32 atomic adds (index_add_, adds per second),
+    each from a 4 GiB table (beyond the L2 and the Infinity Cache) and a
+    2 MiB one (L2-resident).  Seeded indices; the best of `reps` launches."""
+    def best(fn):
+        ts = []
+        for _ in range(reps + 1):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+        return min(ts[1:])
+    out = {}
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    t = best(lambda: dst.copy_(src))
+    out["copy_GBps"] = round(2 * nbytes / t / 1e9, 1)
+    del src, dst
+    g = torch.Generator(device="cpu").manual_seed(7)
+    rows = 1 << 24
+    for label, table_bytes in (("beyond_l2", 1 << 32), ("l2_resident", 1 << 21)):
+        table = torch.ones(table_bytes // 4, dtype=torch.float32, device=dev)
+        # a 16-byte row is read as its four words (torch.take; the row
+        # kernels of index_select run far below the memory system here)
+        idx = torch.randint(0, table.numel() // 4, (rows,), generator=g).to(dev)
+        words = (idx * 4).unsqueeze(1) + torch.arange(4, device=dev)
+        t = best(lambda: torch.take(table, words))
+        out[f"gather16_{label}_rows_per_s"] = float(f"{rows / t:.3g}")
+        del words
+        flat_idx = torch.randint(0, table.numel(), (rows,), generator=g).to(dev)
+        vals = torch.ones(rows, dtype=torch.float32, device=dev)
+        t = best(lambda: table.index_add_(0, flat_idx, vals))
+        out[f"atomic_f32_{label}_per_s"] = float(f"{rows / t:.3g}")
+        itable = table.view(torch.int32)
+        ivals = torch.ones(rows, dtype=torch.int32, device=dev)
+        t = best(lambda: itable.index_add_(0, flat_idx, ivals))
+        out[f"atomic_u32_{label}_per_s"] = float(f"{rows / t:.3g}")
+        del table, idx, flat_idx, vals, ivals, itable
+        torch.cuda.empty_cache()
+    return out
+
+
 def _oracle_rate(orc, rec, budget_s):
     """Whole iterations (insert, update, query) of rec on orc until the time
     budget is used (at least one); returns (records/s, iterations, seconds)."""
@@ -585,6 +635,9 @@ def main():
     ap.add_argument("--gather-calib", action="store_true",
                     help="run only random row gathers of known bytes (32, 64 and 128-byte rows from a "
                          "4 GiB table; calibrates HBM byte counters for random requests)")
+    ap.add_argument("--rates", action="store_true",
+                    help="run only the device-rate probes: streaming copy, random 16-byte row gathers "
+                         "and random binary32/u32 atomics, beyond and within the L2 (torch kernels)")
     args = ap.parse_args()
     TUNED["use"] = not args.untuned
 
@@ -610,6 +663,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes,
                           "launches": 3}), flush=True)
+        return
+    if args.rates:
+        print(json.dumps({"rates": device_rates(torch, dev)}), flush=True)
         return
     if args.gather_calib:
         # 2^24 rows gathered per launch at seeded random row indices from a
