@@ -407,6 +407,45 @@ def test_tunable_launch_parameters_keep_parity(psf, torch_cuda, bin_per, part_lo
     assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
 
 
+@pytest.mark.parametrize("part_log2", [11, 12])
+@pytest.mark.parametrize("extra", [{}, {"flags": 8}, {"weighted": 1}])
+def test_separate_insert_and_update_wide_merge_blocks(psf, torch_cuda, part_log2, extra):
+    """The unfused merge (separate insert and update calls) at the partition
+    widths whose LDS leaves one block per CU (4096 slots; 2048 with the
+    variance's or the weights' further sum), where the merge runs 1024
+    threads per block; against the oracle."""
+    from synth import workloads as W
+    wl = W.plain()
+    g = dict(wl["gen"], width=320, height=180)
+    sc = W.make_scene(wl)
+    cfg = dict(wl["table"], log2_slots=20)
+    if part_log2 == 12 and extra:
+        pytest.skip("2^12-slot partitions hold no further sum")
+    orc = _oracle(dict(cfg, **({"weighted": 1} if extra.get("weighted") else {})))
+    t = _table(psf, cfg, insert_mode=2, part_log2=part_log2, **extra)
+    for it in range(2):
+        rec = sc.generate(g, it)
+        orc.insert(rec)
+        orc.update()
+        d = to_device(rec)
+        t.insert(d)
+        t.update()
+    out, found = t.query(d)
+    torch_cuda.cuda.synchronize()
+    assert t.stats()["dropped"] == 0
+    ge, oe = t.export(), orc.export()
+    assert np.array_equal(ge["keys"], oe["keys"])
+    if extra.get("weighted"):
+        # binary32 weight sums against binary64 ones
+        assert rel_err(ge["c_old"], oe["c_old"]).max() <= RTOL_F32
+    else:
+        assert np.array_equal(ge["c_old"].astype(np.uint64), oe["c_old"])
+    assert rel_err(ge["L"], oe["L"]).max() <= RTOL_F32
+    w_out, w_found = orc.query(rec)
+    assert np.array_equal(found.cpu().numpy(), w_found)
+    assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+
+
 # ----------------------------------------------------------------- fused query
 def _fused_cases():
     # (label, config overrides, record transform)
