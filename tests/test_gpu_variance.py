@@ -230,6 +230,35 @@ def test_variance_after_resets(env, how):
     _compare_variance(t, orc, RTOL, how)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_variance_edge_inputs(env, mode):
+    """An empty launch changes nothing; one record gives variance 0; two
+    records of one cell give the population variance of their luminances;
+    a 256-slot table (one partition)."""
+    import oracle
+    from tests.helpers import records
+    torch, psf = env
+    cfg = dict(log2_slots=8, alpha_mode=psf.PSF_ALPHA_CONST, alpha=0.5)
+    t = psf.Table(**dict(cfg, insert_mode=mode, flags=psf.PSF_FLAG_TRACK_VARIANCE))
+    orc = oracle.Oracle(**cfg)
+    empty = records(0)
+    t.iterate(to_device(empty))
+    k, v = t.export_variance()
+    assert k.size == 0
+    one = records(1, px=0.5, py=0.5, pz=0.5, r=2.0, g=1.0, b=0.5)
+    t.iterate(to_device(one))
+    orc.insert(one)
+    orc.update()
+    k, v = t.export_variance()
+    assert k.size == 1 and v[0] == 0.0
+    two = records(2, px=0.5, py=0.5, pz=0.5, r=[0.0, 0.0], g=[0.0, 2.0], b=[0.0, 0.0])
+    t.iterate(to_device(two))
+    orc.insert(two)
+    orc.update()
+    torch.cuda.synchronize()
+    _compare_variance(t, orc, RTOL, f"edge mode {mode}")
+
+
 def test_variance_argument_checks(env):
     torch, psf = env
     with pytest.raises(psf.PsfError) as e:
