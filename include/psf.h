@@ -118,10 +118,13 @@ enum {
  * (alpha = 1, a cell's first blend or one after a counter reset: V = s2).
  * V is then the population variance of every sample the cell has blended,
  * frame j's samples each weighted beta_j / n_j (beta_j the weight Eq. 10-11
- * gives frame j's mean in the approximant).  Memory: 12 more bytes per slot.
- * The partitioned insert stages every record as its own entry in such a
- * table (no pre-merge of neighbouring duplicates) and its merge pass holds
- * a further binary64 sum per slot in LDS (46 instead of 38 bytes). */
+ * gives frame j's mean in the approximant).  Memory: 12 more bytes per slot
+ * and 4 per staged entry.  The partitioned insert stages each entry's sum
+ * of squared luminances (records of one cell in neighbouring pixels are
+ * pre-merged as in other tables with the default 8 records per binning
+ * thread; with more, each record stays an entry of its own) and its merge
+ * pass holds a further binary64 sum per slot in LDS (46 instead of 38
+ * bytes). */
 
 /* Kernel kinds reported by psf_kernel_times. */
 enum {

@@ -158,7 +158,7 @@ bool validate(const psf_config* c, std::string* why) {
 
 struct Layout {
   size_t sh = 0, sh_acc = 0, var = 0, acc_q = 0;
-  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_v = 0, runs = 0,
+  size_t stats = 0, touch = 0, slots = 0, keys = 0, acc = 0, stage_key = 0, stage_v = 0, stage_q = 0, runs = 0,
          runs_t = 0, perm = 0, total = 0;
   uint32_t part_log2 = 0;
   bool part = false;
@@ -214,6 +214,10 @@ Layout layout_of(const psf_config& c) {
     off = align_up(off + L.cap * 8, 256);
     L.stage_v = off;
     off = align_up(off + L.cap * 16, 256);
+    if (c.flags & PSF_FLAG_TRACK_VARIANCE) {
+      L.stage_q = off;
+      off = align_up(off + L.cap * 4, 256);
+    }
     L.runs = off;
     off = align_up(off + (P + 1) * (uint64_t)L.tiles * 4, 256);
     L.runs_t = off;  // rows padded to a multiple of 4 tiles (16-byte loads)
@@ -398,6 +402,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if (L.part) {
     t->pv.stage_key = reinterpret_cast<unsigned long long*>(b + L.stage_key);
     t->pv.stage_v = reinterpret_cast<float4*>(b + L.stage_v);
+    t->pv.stage_q = L.stage_q ? reinterpret_cast<float*>(b + L.stage_q) : nullptr;
     t->pv.weights = 0;
     t->pv.runs = reinterpret_cast<uint32_t*>(b + L.runs);
     t->pv.runs_t = reinterpret_cast<uint32_t*>(b + L.runs_t);

@@ -27,6 +27,8 @@ struct PartView {
                                   // as a float; n = 0 marks an entry staged for lookup
                                   // only (a rejected sample).  The fused query writes
                                   // each entry's answer {r, g, b, 0} over it.
+  float* stage_q;                 // per staged entry, the sum of its records' squared
+                                  // luminances (tables that keep the variance; else null)
   uint32_t weights;               // this launch's records carry weights (n is then a
                                   // weight, one record per entry)
   uint32_t* runs;                 // [tile][partition + 1]: exclusive offsets in the tile

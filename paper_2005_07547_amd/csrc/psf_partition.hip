@@ -145,9 +145,13 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
   const bool wtd = weighted(tv);
-  // records merge into runs only with integer counters and no weights, and
-  // not where the merge needs each sample's own squared luminance
-  const bool premerge = !kW && !tv.var;
+  // records merge into runs only with integer counters and no weights; a
+  // table that keeps the variance also sums each run's squared luminances
+  // (in registers: with 8 records per thread; with more, its records stay
+  // entries of their own)
+  const bool var = tv.var != nullptr;
+  constexpr bool kQRuns = kPer <= 8;
+  const bool premerge = !kW && (kQRuns || !var);
   for (uint32_t p = tid; p <= P; p += kBinThreads) s_hist[p] = 0;
   __syncthreads();
 
@@ -156,6 +160,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   // (for a merged record: its run head's); ~0 if the record has no entry
   uint32_t pos[kPer];
   float rgb[kPer][3];
+  float qs[kQRuns ? kPer : 1];  // squared luminance (variance tables), summed over runs like rgb
   uint32_t n_skip = 0, n_ovf = 0;
   // flags riding in the top bits of a position (partition < 2^13 before the
   // scan, position < 2^14 after it): merged into the previous lane's entry;
@@ -221,6 +226,13 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   for (uint32_t j = 0; j < kPer; ++j) {
     const bool smp = pos[j] != ~0u && !(pos[j] & kPosLookupOnly);
     bool tail = false;
+    if (kQRuns) {
+      qs[kQRuns ? j : 0] = 0.0f;
+      if (var) {
+        const float y = luma32(rgb[j][0], rgb[j][1], rgb[j][2]);
+        qs[kQRuns ? j : 0] = y * y;
+      }
+    }
     if (premerge) {
       // a sample whose key equals the previous lane's (also a sample)
       // continues that lane's run
@@ -238,12 +250,14 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
           const float vr = __shfl_down(rgb[j][0], d);
           const float vg = __shfl_down(rgb[j][1], d);
           const float vb = __shfl_down(rgb[j][2], d);
+          const float vq = (kQRuns && var) ? __shfl_down(qs[kQRuns ? j : 0], d) : 0.0f;
           const bool same = lane + d < 64 &&
                             ((cont >> (lane + 1)) & ((1ull << d) - 1ull)) == ((1ull << d) - 1ull);
           if (same) {
             rgb[j][0] += vr;
             rgb[j][1] += vg;
             rgb[j][2] += vb;
+            if (kQRuns) qs[kQRuns ? j : 0] += vq;
           }
           live &= live >> d;
         }
@@ -311,6 +325,22 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
     }
     return (pos[j] & kPosLookupOnly) ? 0u : c;
   };
+  if (var) {
+    // each entry's squared-luminance sum, at its staged position (a record
+    // of its own: its value's)
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      if (!own_entry(j)) continue;
+      float q;
+      if (kQRuns) {
+        q = qs[kQRuns ? j : 0];
+      } else {
+        const float y = luma32(rgb[j][0], rgb[j][1], rgb[j][2]);
+        q = y * y;
+      }
+      pv.stage_q[t0 + (pos[j] & kPosBits)] = q;
+    }
+  }
   float wn[kW ? kPer : 1];
   if (kW) {
     // The weights are first read here.  A sample whose weight is not finite
@@ -445,11 +475,11 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   // key[B] | cnt[B] | sum[3][B] (binary64: LDS f64 atomics are both faster
   // than f32 ones on gfx950 and exact enough to make the sum order
   // immaterial), then, in a table that keeps the luminance variance or has
-  // weighted counters, sumx[B]: the squared luminances, or the weights
-  // (binary64 like the value sums, rounded once to binary32 at the
-  // write-back, so the counters do not depend on the order of the atomics;
-  // cnt then only marks the slots touched).  Every entry is one record in
-  // such tables.  After the blend the sums hold the cells' new values.
+  // weighted counters, sumx[B]: the squared luminances (staged per entry),
+  // or the weights (binary64 like the value sums, rounded once to binary32
+  // at the write-back, so the counters do not depend on the order of the
+  // atomics; cnt then only marks the slots touched; every entry is one
+  // record).  After the blend the sums hold the cells' new values.
   // Last, list[B] (16-bit): the touched slots, gathered for the write-back.
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_dropped, s_nlist, s_sat;
@@ -603,6 +633,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
   bool ev0[kEntryBatch];
   unsigned long long ek0[kEntryBatch];
   float4 v0[kEntryBatch];
+  float q0[kEntryBatch];  // variance tables: the entries' squared-luminance sums
   if (w_lo < w_hi) {
     ch0 = chunk_of(w_lo);
     batch_of(ch0, 0, at0, ev0);
@@ -610,6 +641,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       ek0[q] = pv.stage_key[at0[q]];
       v0[q] = pv.stage_v[at0[q]];
+      q0[q] = var ? pv.stage_q[at0[q]] : 0.0f;
     }
   }
 #pragma unroll
@@ -635,7 +667,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
     for (uint32_t q = 0; q < kEntryBatch; ++q) keep_at[b][q] = keep_slot[b][q] = ~0u;
 
   auto accumulate = [&](const uint64_t* at, const bool* ev, const unsigned long long* ek, const float4* v,
-                        uint32_t nb) {
+                        const float* qv, uint32_t nb) {
 #pragma unroll
     for (uint32_t q = 0; q < kEntryBatch; ++q) {
       uint32_t slot = ~0u;
@@ -670,10 +702,7 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
           atomicAdd(&s_sum0[slot], (double)v[q].x);
           atomicAdd(&s_sum1[slot], (double)v[q].y);
           atomicAdd(&s_sum2[slot], (double)v[q].z);
-          if (var) {
-            const double y = luma64(v[q].x, v[q].y, v[q].z);
-            atomicAdd(&s_sumx[slot], y * y);
-          }
+          if (var) atomicAdd(&s_sumx[slot], (double)qv[q]);
         }
       }
       if (results) {
@@ -699,9 +728,10 @@ __device__ __forceinline__ void merge_body(const TableView& tv, const PartView& 
         for (uint32_t q = 0; q < kEntryBatch; ++q) {
           ek0[q] = pv.stage_key[at0[q]];
           v0[q] = pv.stage_v[at0[q]];
+          q0[q] = var ? pv.stage_q[at0[q]] : 0.0f;
         }
       }
-      accumulate(at0, ev0, ek0, v0, batches);
+      accumulate(at0, ev0, ek0, v0, q0, batches);
     }
   }
   __syncthreads();
