@@ -230,6 +230,26 @@ def test_variance_after_resets(env, how):
     _compare_variance(t, orc, RTOL, how)
 
 
+def test_variance_insert_split_over_staging_capacity(env):
+    """A frame larger than the partitioned insert's staging (max_batch 4096,
+    8192 records) is inserted in chunks whose squared-luminance sums meet in
+    the pending accumulator before the blend."""
+    import oracle
+    torch, psf = env
+    wl, frames = _tiny_frames(3, 0)
+    t = psf.Table(**dict(wl["table"], insert_mode=psf.PSF_INSERT_PARTITIONED, max_batch=4096,
+                         flags=psf.PSF_FLAG_TRACK_VARIANCE))
+    orc = oracle.Oracle(**wl["table"])
+    for rec in frames:
+        assert len(rec["px"]) > 4096
+        t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+    torch.cuda.synchronize()
+    compare_cells(t.export(), orc.export(), RTOL, "split")
+    _compare_variance(t, orc, RTOL, "split")
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_variance_edge_inputs(env, mode):
     """An empty launch changes nothing; one record gives variance 0; two
