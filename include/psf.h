@@ -89,7 +89,7 @@ enum { PSF_RESET_COUNTERS = 1u, PSF_RESET_CLEAR = 2u, PSF_RESET_STATS = 4u };
 /* Insert strategies (psf_config.insert_mode). */
 enum {
   PSF_INSERT_AUTO = 0,        /* library choice: partitioned when the table
-                                 has at most 8192 partitions, else direct */
+                                 has at most 16384 partitions, else direct */
   PSF_INSERT_DIRECT = 1,      /* wave-merged global CAS/atomics per record */
   PSF_INSERT_PARTITIONED = 2  /* bin by table partition, aggregate in LDS */
 };
@@ -176,12 +176,12 @@ typedef struct psf_config {
   int32_t insert_mode;       /* PSF_INSERT_* */
   uint32_t part_log2;        /* partitioned insert: log2 slots per partition
                                 (0 = default: 11, or 12 for tables of 2^25
-                                slots; else 8..12.  With
+                                slots or more; else 8..12.  With
                                 PSF_FLAG_TRACK_VARIANCE or weighted = 1:
                                 default 10, or 11 for tables of 2^24
-                                slots; at most 11).
-                                A table of more than 8192 partitions takes
-                                the direct strategy. */
+                                slots or more; at most 11).  A table of
+                                more than 16384 partitions takes the direct
+                                strategy. */
   uint64_t max_batch;        /* partitioned insert: records binned per launch
                                 (0 = default 4M, at most 2^31); larger
                                 inserts are split */

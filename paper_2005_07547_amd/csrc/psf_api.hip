@@ -114,7 +114,14 @@ hipError_t timed(psf_table* t, int kind, hipStream_t s, F&& launch) {
 constexpr uint32_t kDefaultPartLog2 = 11;
 constexpr uint32_t kDefaultBinPer = 8;
 constexpr uint64_t kDefaultBatch = 1ull << 22;
-constexpr uint32_t kMaxPartitions = 1u << 13;  // LDS histogram of the binning pass
+// Partitions of a partitioned table: at most 2^14 (beyond, the merge
+// streams so much key mirror per frame, 8 bytes a slot, that the direct
+// strategy is faster: 2^27 slots took 1.45 ms partitioned against 1.20 ms
+// direct on the plain workload, 2^26 slots 0.78 against 0.96 ms), and the
+// default width is raised until there are at most 2^13 (the binning pass's
+// LDS histogram then takes 32 KB).
+constexpr uint32_t kMaxPartitions = 1u << 14;
+constexpr uint32_t kDefaultPartitions = 1u << 13;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -177,7 +184,7 @@ Layout layout_of(const psf_config& c) {
   const bool extra = (c.flags & PSF_FLAG_TRACK_VARIANCE) || c.weighted;
   const uint32_t widest = extra ? 11u : 12u;
   uint32_t def = extra ? kDefaultPartLog2 - 1 : kDefaultPartLog2;
-  while (def < widest && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kMaxPartitions) ++def;
+  while (def < widest && c.log2_slots > def && (1ull << (c.log2_slots - def)) > kDefaultPartitions) ++def;
   L.part_log2 = c.part_log2 ? c.part_log2 : def;
   if (L.part_log2 > c.log2_slots) L.part_log2 = c.log2_slots;
   const uint64_t P = 1ull << (c.log2_slots - L.part_log2);

@@ -69,7 +69,7 @@ struct alignas(16) BlockTouch {
   uint32_t pad;
   unsigned long long total;
 };
-constexpr uint32_t kTouchEntries = 8192;
+constexpr uint32_t kTouchEntries = 1u << 14;
 
 // Two-band SH payload (Sec. 2.6): a cell's state, the four luminance
 // coefficients and the chroma pair (24 bytes, padded to 32), and its frame

@@ -162,8 +162,9 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   float rgb[kPer][3];
   float qs[kQRuns ? kPer : 1];  // squared luminance (variance tables), summed over runs like rgb
   uint32_t n_skip = 0, n_ovf = 0;
-  // flags riding in the top bits of a position (partition < 2^13 before the
-  // scan, position < 2^14 after it): merged into the previous lane's entry;
+  // flags riding in the top bits of a position (partition << 13 | rank, the
+  // partition < 2^15 and the rank < 2^13, before the scan; the position in
+  // the tile < 2^13 after it): merged into the previous lane's entry;
   // with weights, staged for lookup only and counted as a coordinate overflow
   constexpr uint32_t kPosTail = 1u << 29, kPosLookupOnly = 1u << 31, kPosOverflow = 1u << 30;
   constexpr uint32_t kPosBits = kPosTail - 1;
@@ -270,7 +271,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
     }
     const uint32_t p = partition_of(fmix64(key[j] & ~kLookupOnlyBit), tv.log2_slots, tv.part_log2);
     const uint32_t rank = atomicAdd(&s_hist[p], 1u);
-    pos[j] |= (p << 16) | rank;
+    pos[j] |= (p << 13) | rank;
   }
   // rare-event counters: one atomic per wave when non-zero (with weights,
   // after the staging pass has judged them)
@@ -294,7 +295,7 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   for (uint32_t j = 0; j < kPer; ++j) {
     if (pos[j] != ~0u && !(pos[j] & kPosTail)) {
       const uint32_t q = pos[j] & ((1u << 29) - 1u);
-      pos[j] = (s_hist[q >> 16] + (q & 0xffffu)) | (pos[j] & ~((1u << 29) - 1u));
+      pos[j] = (s_hist[q >> 13] + (q & 0x1fffu)) | (pos[j] & ~((1u << 29) - 1u));
     }
     if (premerge && pv.perm) {
       // a merged record is answered from its run head's entry

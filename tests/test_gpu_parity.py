@@ -620,10 +620,38 @@ def test_multi_level_lookup(psf, torch_cuda):
     assert int((w_level >= 2).sum()) > 0 and int((w_level == 0).sum()) < len(w_level)
 
 
+@pytest.mark.parametrize("log2_slots,part_log2", [(26, 0), (25, 11)])
+def test_more_than_8192_partitions_stay_partitioned(psf, torch_cuda, log2_slots, part_log2):
+    """Tables of 16384 partitions (2^26 slots by default, 2^25 of 2048) stay
+    on the partitioned strategy (the binning pass's histogram then takes 64
+    KB of LDS); against the oracle on the plain scene at reduced resolution,
+    with the fused answers."""
+    from synth import workloads as W
+    wl = W.plain()
+    g = dict(wl["gen"], width=320, height=180)
+    sc = W.make_scene(wl)
+    cfg = dict(wl["table"], log2_slots=log2_slots)
+    orc = _oracle(cfg)
+    t = psf.Table(**cfg, part_log2=part_log2, flags=psf.PSF_FLAG_TIMING)
+    for it in range(2):
+        rec = sc.generate(g, it)
+        out, found = t.iterate(to_device(rec))
+        orc.insert(rec)
+        orc.update()
+    torch_cuda.cuda.synchronize()
+    w_out, w_found = orc.query(rec)
+    assert np.array_equal(found.cpu().numpy(), w_found)
+    assert rel_err(out.cpu().numpy(), w_out).max() <= RTOL_F32
+    assert {"bin", "merge_blend"} <= set(t.kernel_times())
+    assert t.stats()["dropped"] == 0
+    compare_cells(t.export(), orc.export(), RTOL_F32, f"2^{log2_slots} slots")
+    t.close()
+
+
 def test_large_table_default_partitions_stay_partitioned(psf, torch_cuda):
     """A 2^25-slot table with the default partition width takes 4096-slot
-    partitions (at most 8192 of them), so the automatic strategy stays
-    partitioned; results match the oracle."""
+    partitions (8192 of them), so the automatic strategy stays partitioned;
+    results match the oracle."""
     wl, _ = _tiny(0)
     cfg = dict(wl["table"], log2_slots=25)
     orc = _oracle(cfg)
