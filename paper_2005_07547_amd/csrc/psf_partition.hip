@@ -15,11 +15,14 @@
 //            record's entry position in the tile);
 //   (transpose -- for large launches, the offset table turned so that a
 //            partition's offsets are one row);
-//   merge -- one block per partition loads the partition's keys into LDS,
-//            gathers that partition's entries from every tile, finds or
-//            claims each key's slot and accumulates count (u32, or binary32
-//            weight sums) and sums (binary64) with LDS atomics, then writes
-//            the partition back:
+//   merge -- one block per partition (512 threads, or 1024 where the
+//            partition's LDS leaves room for one block per CU) loads the
+//            partition's keys into LDS, gathers that partition's entries
+//            from every tile, finds or claims each key's slot and
+//            accumulates count (u32) and sums (binary64; also the weights
+//            of a weighted table and the squared luminances of one that
+//            keeps the variance) with LDS atomics, lists the touched
+//            slots, then writes them back:
 //            either adding into the global accumulators (plain insert) or,
 //            when the whole frame is in this launch, applying the temporal
 //            blend (Eq. 10-11) directly so the accumulators never touch HBM;
