@@ -114,12 +114,13 @@ hipError_t timed(psf_table* t, int kind, hipStream_t s, F&& launch) {
 constexpr uint32_t kDefaultPartLog2 = 11;
 constexpr uint32_t kDefaultBinPer = 8;
 constexpr uint64_t kDefaultBatch = 1ull << 22;
-// Partitions of a partitioned table: at most 2^14 (beyond, the merge
-// streams so much key mirror per frame, 8 bytes a slot, that the direct
-// strategy is faster: 2^27 slots took 1.45 ms partitioned against 1.20 ms
-// direct on the plain workload, 2^26 slots 0.78 against 0.96 ms), and the
-// default width is raised until there are at most 2^13 (the binning pass's
-// LDS histogram then takes 32 KB).
+// Partitions of a partitioned table: at most 2^14 (beyond, the merge's
+// fixed work per partition, its column of the run table over every tile,
+// LDS set-up and barrier-separated phases, outweighs what it saves: 2^27
+// slots took 1.45 ms partitioned against 1.20 ms direct on the plain
+// workload, 2^26 slots 0.78 against 0.96 ms), and the default width is
+// raised until there are at most 2^13 (the binning pass's LDS histogram
+// then takes 32 KB).
 constexpr uint32_t kMaxPartitions = 1u << 14;
 constexpr uint32_t kDefaultPartitions = 1u << 13;
 
