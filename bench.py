@@ -530,8 +530,11 @@ def form_serving(torch, psf, W, n_sessions=48, rate=20.0, budget_gb=200.0, frame
         sc = Scene(Scene.RANDOM, seed=seed, glossy_frac=-1.0 if sid % 2 else 0.5)
         frames = [_dev(sc.generate(gen, f), torch) for f in range(frames_per_session)]
         log2 = int(min(25, max(16, math.ceil(math.log2(w * h * 4)) + 1)))
-        cfg = dict(wl["table"], log2_slots=log2,
-                   kappa=W.kappa_for(60.0, h, 8.0 * math.sqrt(2.0), -5))
+        # sessions take the launch parameters tuned for the batched form
+        # (many uneven sessions sharing launches)
+        cfg = with_params(dict(wl["table"], log2_slots=log2,
+                               kappa=W.kappa_for(60.0, h, 8.0 * math.sqrt(2.0), -5)),
+                          tuned("batched-16"))
         reqs.append(serving.SessionRequest(sid=sid, arrival=arrival, iterations=iters, table_cfg=cfg,
                                            frames=frames, records=w * h * 4))
     srv = serving.Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=64)
