@@ -147,7 +147,6 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   unsigned long long* s_k = reinterpret_cast<unsigned long long*>(s_dyn_bin);
   const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   const uint64_t t0 = (uint64_t)tile * (kBinThreads * kPer);
-  const bool wtd = weighted(tv);
   // records merge into runs only with integer counters and no weights; a
   // table that keeps the variance also sums each run's squared luminances
   // (in registers: with 8 records per thread; with more, its records stay
@@ -174,7 +173,10 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
   const bool hr = rec.rough != nullptr;
   // Every load is unconditional (indices past the end are clamped, absent
   // arrays alias the positions) so that a batch of records is a single
-  // memory round trip; validity is applied afterwards.
+  // memory round trip; validity is applied afterwards.  The records are read
+  // once: non-temporal loads keep them from evicting what the merge pass
+  // reads next from the caches (the staged entries, the key mirror, the
+  // slots).
   const float* p_ox = hr ? rec.ox : rec.px;
   const float* p_oy = hr ? rec.oy : rec.px;
   const float* p_oz = hr ? rec.oz : rec.px;
@@ -188,20 +190,20 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint64_t i = t0 + (uint64_t)(j0 + q) * kBinThreads + tid;
       const uint64_t ic = i < n ? i : n - 1;
-      f[q][0] = rec.px[ic];
-      f[q][1] = rec.py[ic];
-      f[q][2] = rec.pz[ic];
-      f[q][3] = rec.nx[ic];
-      f[q][4] = rec.ny[ic];
-      f[q][5] = rec.nz[ic];
-      f[q][6] = p_ox[ic];
-      f[q][7] = p_oy[ic];
-      f[q][8] = p_oz[ic];
-      f[q][9] = rec.r[ic];
-      f[q][10] = rec.g[ic];
-      f[q][11] = rec.b[ic];
-      f[q][12] = p_ro[ic];
-      fp[q] = kFp ? rec.footprint[ic] : 0.0f;
+      f[q][0] = __builtin_nontemporal_load(rec.px + ic);
+      f[q][1] = __builtin_nontemporal_load(rec.py + ic);
+      f[q][2] = __builtin_nontemporal_load(rec.pz + ic);
+      f[q][3] = __builtin_nontemporal_load(rec.nx + ic);
+      f[q][4] = __builtin_nontemporal_load(rec.ny + ic);
+      f[q][5] = __builtin_nontemporal_load(rec.nz + ic);
+      f[q][6] = __builtin_nontemporal_load(p_ox + ic);
+      f[q][7] = __builtin_nontemporal_load(p_oy + ic);
+      f[q][8] = __builtin_nontemporal_load(p_oz + ic);
+      f[q][9] = __builtin_nontemporal_load(rec.r + ic);
+      f[q][10] = __builtin_nontemporal_load(rec.g + ic);
+      f[q][11] = __builtin_nontemporal_load(rec.b + ic);
+      f[q][12] = __builtin_nontemporal_load(p_ro + ic);
+      fp[q] = kFp ? __builtin_nontemporal_load(rec.footprint + ic) : 0.0f;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
@@ -924,7 +926,8 @@ __global__ void __launch_bounds__(kThreads) k_merge(TableView tv, PartView pv, u
 // the tile's staged entries (their positions in pv.perm).  The tile's staged
 // values are read into LDS with 16-byte loads, then every thread answers
 // four consecutive records at a time (8-byte perm loads, 16-byte stores when
-// the output rows are 16-byte aligned).
+// the output rows are 16-byte aligned; non-temporal, since no kernel of the
+// iteration reads the answers again).
 constexpr uint32_t kUnstageThreads = 512;
 
 __device__ __forceinline__ void unstage_one(const float* s_res, uint32_t count, uint32_t pos, float& r,
@@ -974,9 +977,10 @@ __device__ __forceinline__ void unstage_body(const PartView& pv, uint32_t P, uin
       }
     }
     if (vec && i + 4 <= end) {
-      *reinterpret_cast<float4*>(out + i) = make_float4(r[0], r[1], r[2], r[3]);
-      *reinterpret_cast<float4*>(out + n + i) = make_float4(g[0], g[1], g[2], g[3]);
-      *reinterpret_cast<float4*>(out + 2 * n + i) = make_float4(b[0], b[1], b[2], b[3]);
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(v4f{r[0], r[1], r[2], r[3]}, reinterpret_cast<v4f*>(out + i));
+      __builtin_nontemporal_store(v4f{g[0], g[1], g[2], g[3]}, reinterpret_cast<v4f*>(out + n + i));
+      __builtin_nontemporal_store(v4f{b[0], b[1], b[2], b[3]}, reinterpret_cast<v4f*>(out + 2 * n + i));
       if (found) *reinterpret_cast<uchar4*>(found + i) = make_uchar4(f[0], f[1], f[2], f[3]);
     } else {
       for (int k = 0; k < 4; ++k) {

@@ -1,4 +1,4 @@
-"""Host-side tooling without a GPU: autotuner search space, rocprofv3 summary
+"""Host-side tooling without a GPU: autotuner search space and ranking, rocprofv3 summary
 parsing, bench contract on a multi-GPU request."""
 import csv
 import json
@@ -18,6 +18,24 @@ def test_autotune_candidates_cover_the_space():
     assert {x["flags"] for x in c} == {0, psf.PSF_FLAG_TRANSPOSE_RUNS}
     d = list(autotune.candidates({"insert_mode": [psf.PSF_INSERT_DIRECT], "bin_per": [8]}))
     assert d == [{"insert_mode": psf.PSF_INSERT_DIRECT}]
+
+
+def test_autotune_keeps_each_candidates_best_round(monkeypatch):
+    # candidate A is slow on its first timing (device drift), B steady: two
+    # rounds rank A first on its better median, one round would pick B
+    from paper_2005_07547_amd import autotune
+    seq = {8: [1.2, 1.0], 12: [1.1, 1.1]}
+
+    def fake(table_cfg, params, bufs, warmup, iters):
+        return {"ms": seq[params["bin_per"]].pop(0), "dropped": 0}
+
+    monkeypatch.setattr(autotune, "time_config", fake)
+    best, res = autotune.tune({}, [], space={"bin_per": [8, 12]})
+    assert best == {"bin_per": 8}
+    assert [r["ms"] for r in res] == [1.0, 1.1]
+    seq.update({8: [1.2], 12: [1.1]})
+    best, _ = autotune.tune({}, [], space={"bin_per": [8, 12]}, rounds=1)
+    assert best == {"bin_per": 12}
 
 
 def _write_counters(d, rows):
