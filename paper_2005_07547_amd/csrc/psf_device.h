@@ -425,18 +425,25 @@ __device__ __forceinline__ uint8_t lookup_finish(const TableView& tv, int32_t dt
   }
 }
 
+// A value a pass reads once, and one it writes that no kernel of the pass
+// reads: non-temporal, so streaming them does not evict from the caches the
+// table the pass gathers from.
+__device__ __forceinline__ float ld_once(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_once(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 // Key of query i of a structure-of-arrays query set (kEmpty if rejected).
 template <class Q>
 __device__ __forceinline__ uint64_t query_key(const KeyParams& kp, const Q& q, uint64_t i, int32_t up = 0) {
   const bool hr = q.rough != nullptr;
-  const float ro = hr ? q.rough[i] : 0.0f;
+  const float ro = hr ? ld_once(q.rough + i) : 0.0f;
   const bool gl = hr && ro < kp.rough_thr;
   const bool hf = q.footprint != nullptr;
   uint64_t key;
   bool ovf;
-  if (!cell_key(kp, q.px[i], q.py[i], q.pz[i], q.nx[i], q.ny[i], q.nz[i], gl ? q.ox[i] : 0.0f,
-                gl ? q.oy[i] : 0.0f, gl ? q.oz[i] : 0.0f, hr, ro, hf, hf ? q.footprint[i] : 0.0f, key, ovf,
-                up))
+  if (!cell_key(kp, ld_once(q.px + i), ld_once(q.py + i), ld_once(q.pz + i), ld_once(q.nx + i),
+                ld_once(q.ny + i), ld_once(q.nz + i), gl ? ld_once(q.ox + i) : 0.0f,
+                gl ? ld_once(q.oy + i) : 0.0f, gl ? ld_once(q.oz + i) : 0.0f, hr, ro, hf,
+                hf ? ld_once(q.footprint + i) : 0.0f, key, ovf, up))
     return kEmpty;
   return key;
 }

@@ -107,18 +107,19 @@ __global__ void __launch_bounds__(kInsBlock) k_insert_direct(RecPtrs rec, uint64
   float r = 0.0f, g = 0.0f, b = 0.0f, w = 1.0f;
   if (i < n) {
     const bool hr = rec.rough != nullptr;
-    const float ro = hr ? rec.rough[i] : 0.0f;
+    const float ro = hr ? ld_once(rec.rough + i) : 0.0f;
     const bool gl = hr && ro < kp.rough_thr;
-    r = rec.r[i];
-    g = rec.g[i];
-    b = rec.b[i];
+    r = ld_once(rec.r + i);
+    g = ld_once(rec.g + i);
+    b = ld_once(rec.b + i);
     const bool hf = rec.footprint != nullptr;
-    valid = cell_key(kp, rec.px[i], rec.py[i], rec.pz[i], rec.nx[i], rec.ny[i], rec.nz[i],
-                     gl ? rec.ox[i] : 0.0f, gl ? rec.oy[i] : 0.0f, gl ? rec.oz[i] : 0.0f, hr, ro, hf,
-                     hf ? rec.footprint[i] : 0.0f, key, ovf);
+    valid = cell_key(kp, ld_once(rec.px + i), ld_once(rec.py + i), ld_once(rec.pz + i), ld_once(rec.nx + i),
+                     ld_once(rec.ny + i), ld_once(rec.nz + i), gl ? ld_once(rec.ox + i) : 0.0f,
+                     gl ? ld_once(rec.oy + i) : 0.0f, gl ? ld_once(rec.oz + i) : 0.0f, hr, ro, hf,
+                     hf ? ld_once(rec.footprint + i) : 0.0f, key, ovf);
     valid = valid && finite3(r, g, b);
     if (rec.weight) {
-      w = rec.weight[i];
+      w = ld_once(rec.weight + i);
       valid = valid && __builtin_isfinite(w) && w > 0.0f;
       r *= w;
       g *= w;
@@ -245,9 +246,9 @@ __global__ void __launch_bounds__(256) k_query(QryPtrs q, uint64_t n, KeyParams 
   if (i >= n) return;
   float rgb[3];
   const uint8_t hit = lookup_key(tv, dtype, query_key(kp, q, i), rgb);
-  out[i] = rgb[0];
-  out[n + i] = rgb[1];
-  out[2 * n + i] = rgb[2];
+  st_once(out + i, rgb[0]);
+  st_once(out + n + i, rgb[1]);
+  st_once(out + 2 * n + i, rgb[2]);
   if (found) found[i] = hit;
 }
 
@@ -305,8 +306,8 @@ __global__ void __launch_bounds__(kEstThreads) k_estimate(EstPtrs a, uint64_t n,
     float L[3], h[3];
     const uint8_t fo = lookup_finish(tv_o, dt_o, lo[v], L);
     const uint8_t fi = lookup_finish(tv_i, dt_i, li[v], h);
-    const float g[3] = {a.gr[i], a.gg[i], a.gb[i]};
-    const float w = a.wp[i];
+    const float g[3] = {ld_once(a.gr + i), ld_once(a.gg + i), ld_once(a.gb + i)};
+    const float w = ld_once(a.wp + i);
     const bool both = fo && fi;
     float e[3];
 #pragma unroll
@@ -321,9 +322,9 @@ __global__ void __launch_bounds__(kEstThreads) k_estimate(EstPtrs a, uint64_t n,
         e[c] = corr + L[c];
       }
     }
-    out[i] = e[0];
-    out[n + i] = e[1];
-    out[2 * n + i] = e[2];
+    st_once(out + i, e[0]);
+    st_once(out + n + i, e[1]);
+    st_once(out + 2 * n + i, e[2]);
     if (applied) applied[i] = both ? 1 : 0;
   }
 }
@@ -338,8 +339,9 @@ __global__ void __launch_bounds__(256) k_step_samples(StepPtrs a, uint64_t n, Ke
   float L[3];
   lookup_key(tv, dtype, query_key(kp, a.next, i), L);
   const bool le = a.le_r != nullptr;
-  const float e[3] = {le ? a.le_r[i] : 0.0f, le ? a.le_g[i] : 0.0f, le ? a.le_b[i] : 0.0f};
-  const float t[3] = {a.t_r[i], a.t_g[i], a.t_b[i]};
+  const float e[3] = {le ? ld_once(a.le_r + i) : 0.0f, le ? ld_once(a.le_g + i) : 0.0f,
+                      le ? ld_once(a.le_b + i) : 0.0f};
+  const float t[3] = {ld_once(a.t_r + i), ld_once(a.t_g + i), ld_once(a.t_b + i)};
 #pragma unroll
   for (int c = 0; c < 3; ++c) out[(uint64_t)c * n + i] = e[c] + L[c] * t[c];
 }
