@@ -205,6 +205,16 @@ __device__ __forceinline__ void bin_body(const RecPtrs& rec, uint64_t n, const K
       f[q][12] = __builtin_nontemporal_load(p_ro + ic);
       fp[q] = kFp ? __builtin_nontemporal_load(rec.footprint + ic) : 0.0f;
     }
+    // Every loaded value is used here, so the batch's loads all issue
+    // before the first wait: left alone, the compiler sinks some of them
+    // behind the key function's finiteness tests, each such group a
+    // dependent round trip of its own.
+#pragma unroll
+    for (uint32_t q = 0; q < kLoad; ++q) {
+#pragma unroll
+      for (uint32_t k = 0; k < 13; ++k) asm volatile("" : : "v"(f[q][k]));
+      if (kFp) asm volatile("" : : "v"(fp[q]));
+    }
 #pragma unroll
     for (uint32_t q = 0; q < kLoad; ++q) {
       const uint32_t j = j0 + q;

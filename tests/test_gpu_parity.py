@@ -109,6 +109,66 @@ def test_keys_bit_exact_adversarial(psf, kappa, e_min, max_level):
     assert bad.size == 0, f"{bad.size} key mismatches, first at {bad[:5]}"
 
 
+def _octahedral_edges(n, seed):
+    """Normals and directions whose octahedral coordinates (the L1-normalised
+    x and y, or their fold 1 - |.| for z < 0) land on or within a few ulps of
+    every interior bin edge of a 4 x 4 and an 8 x 8 grid, at norms from 2^-90
+    to 2^90, with zero and tiny components mixed in."""
+    rng = np.random.default_rng(seed)
+    edges = np.array([-0.75, -0.5, -0.25, 0.0, 0.25, 0.5, 0.75])
+
+    def vec(size):
+        # target coordinates: an edge for one (or both) of the two, free
+        # otherwise, inside the octahedron |u| + |w| <= 1
+        u = rng.choice(edges, size) + rng.normal(0.0, 1e-3, size) * (rng.random(size) < 0.3)
+        w = rng.uniform(-1.0, 1.0, size) * (1.0 - np.abs(u))
+        both = rng.random(size) < 0.3
+        w = np.where(both, rng.choice(edges, size) * (1.0 - np.abs(u)), w)
+        fold = rng.random(size) < 0.5
+        # folded half: the edge is 1 - |w| for u, so solve |w| = 1 - edge
+        uf = np.where(fold, np.sign(u + 1e-30) * (1.0 - np.abs(rng.choice(edges, size))) * rng.random(size), u)
+        wf = np.where(fold, np.sign(rng.normal(size=size)) * (1.0 - np.abs(u)), w)
+        uf = np.where(fold, np.sign(uf) * np.minimum(np.abs(uf), 1.0 - np.abs(wf)), uf)
+        zz = 1.0 - np.abs(uf) - np.abs(wf)
+        z = np.where(fold, -np.maximum(zz, 0.0), np.maximum(zz, 0.0))
+        scale = np.exp2(rng.integers(-90, 91, size)).astype(np.float64) * rng.uniform(0.5, 2.0, size)
+        v = (np.stack([uf, wf, z]) * scale).astype(np.float32)
+        # nudge one component by up to 3 ulps either way
+        k = rng.integers(-3, 4, size).astype(np.int32)
+        c = rng.integers(0, 3, size)
+        bits = v.view(np.int32)
+        cols = np.arange(size)
+        bits[c, cols] = bits[c, cols] + k * np.where(v[c, cols] == 0, 0, 1)
+        v = bits.view(np.float32)
+        v[0, ::53] = 0.0
+        v[1, 7::59] = np.float32(-1e-44)
+        v[0, 11::61] = np.float32(3e-45)
+        return v
+
+    nrm, dirs = vec(n), vec(n)
+    p = rng.uniform(-4, 4, size=(3, n)).astype(np.float32)
+    rough = np.full(n, 0.1, dtype=np.float32)  # glossy: the direction is binned too
+    return records(n, px=p[0], py=p[1], pz=p[2], nx=nrm[0], ny=nrm[1], nz=nrm[2], ox=dirs[0],
+                   oy=dirs[1], oz=dirs[2], rough=rough)
+
+
+@pytest.mark.parametrize("nb,db", [(2, 3), (1, 2), (2, 1)])
+def test_keys_bit_exact_octahedral_bin_edges(psf, nb, db):
+    cfg = dict(cam=(0.0, 0.0, 0.0), kappa=0.0, e_min=-2, max_level=15, normal_bins_log2=nb,
+               dir_bins_log2=db, rough_thr=0.3)
+    rec = _octahedral_edges(300007, seed=31 + nb * 7 + db)
+    want, _ = _oracle(cfg).keys(rec)
+    got = _table(psf, cfg, log2_slots=8).keys(to_device(rec)).cpu().numpy().view(np.uint64)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} key mismatches, first at {bad[:5]}"
+    # the batch really sits on the edges: a large share of the normals'
+    # unfolded coordinates lie within B 2^-18 of an integer once scaled
+    v = np.stack([rec["nx"], rec["ny"], rec["nz"]]).astype(np.float64)
+    l1 = np.abs(v).sum(axis=0)
+    t = (v[0] / np.where(l1 > 0, l1, 1.0) * 0.5 + 0.5) * 2.0 ** nb
+    assert (np.abs(t - np.rint(t)) <= 2.0 ** (nb - 18)).mean() > 0.1
+
+
 def test_keys_bit_exact_workloads(psf):
     from synth import workloads as W
     for wl in (W.tiny(), W.plain()):
