@@ -102,10 +102,28 @@ enum {
                                   per-tile run table before the merge pass
                                   (by default only tables of 2^22 entries
                                   or more are transposed) */
-  PSF_FLAG_TRACK_VARIANCE = 8u  /* keep a binary32 luminance variance per
+  PSF_FLAG_TRACK_VARIANCE = 8u, /* keep a binary32 luminance variance per
                                   cell (below); RGB payload, unweighted
                                   tables only (NOT_SUPPORTED otherwise) */
+  PSF_FLAG_NO_ACCUMULATORS = 16u /* a table for the fused calls only (below) */
 };
+
+/* Tables without frame accumulators (PSF_FLAG_NO_ACCUMULATORS).  Sec. 2.4's
+ * insert and blend of one frame only need a frame's sums between a separate
+ * psf_insert_samples and psf_temporal_update; psf_iterate (and
+ * psf_progressive_step, psf_iterate_batch) on the partitioned strategy sums
+ * a frame in the merge pass's LDS and blends it there.  Such a table leaves
+ * out the 16-byte per-slot accumulator (and, with
+ * PSF_FLAG_TRACK_VARIANCE, the 8-byte pending squared-luminance sum):
+ * 40 bytes per slot for the cell state and key mirror instead of 56.
+ * Requirements: RGB payload and an insert_mode other than DIRECT, and a
+ * table narrow enough for the partitioned strategy (psf_table_bytes
+ * returns 0 and psf_create_table NOT_SUPPORTED otherwise).  On such a table
+ * psf_insert_samples and psf_temporal_update return NOT_SUPPORTED, as does
+ * psf_iterate with more records than max_batch (a launch that would be
+ * split); psf_iterate with no records blends nothing and only answers the
+ * queries.  Lookups, resets and exports work as on any table; exported
+ * n_new is 0 (no frame is ever pending). */
 
 /* Per-cell luminance variance (PSF_FLAG_TRACK_VARIANCE).  The paper keeps
  * none; this library's reading: the spread of a cell's samples around its

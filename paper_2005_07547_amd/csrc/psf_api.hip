@@ -155,8 +155,11 @@ bool validate(const psf_config* c, std::string* why) {
   if (((c->flags & PSF_FLAG_TRACK_VARIANCE) || c->weighted) && c->part_log2 == 12)
     return bad("part_log2 must be at most 11 in a weighted table or one that keeps the variance");
   if (c->flags & ~(uint32_t)(PSF_FLAG_PROBE_STATS | PSF_FLAG_TIMING | PSF_FLAG_TRANSPOSE_RUNS |
-                             PSF_FLAG_TRACK_VARIANCE))
+                             PSF_FLAG_TRACK_VARIANCE | PSF_FLAG_NO_ACCUMULATORS))
     return bad("unknown flags");
+  if ((c->flags & PSF_FLAG_NO_ACCUMULATORS) &&
+      (c->payload != PSF_PAYLOAD_RGB || c->insert_mode == PSF_INSERT_DIRECT))
+    return bad("a table without accumulators takes the RGB payload and the partitioned strategy");
   if (c->max_batch > (1ull << 31)) return bad("max_batch must be <= 2^31");
   if (c->bin_per != 0 && !psf::bin_per_ok(c->bin_per)) return bad("bin_per must be 0, 8, 12 or 16");
   if (c->payload > PSF_PAYLOAD_SH2_YCOCG) return bad("payload must be RGB or SH2_YCOCG");
@@ -199,8 +202,11 @@ Layout layout_of(const psf_config& c) {
   off = align_up(off + S * sizeof(psf::Slot), 256);
   L.keys = off;
   off = align_up(off + S * 8, 256);
-  L.acc = off;
-  off = align_up(off + S * sizeof(psf::Acc), 256);
+  const bool no_acc = (c.flags & PSF_FLAG_NO_ACCUMULATORS) != 0;
+  if (!no_acc) {
+    L.acc = off;
+    off = align_up(off + S * sizeof(psf::Acc), 256);
+  }
   if (c.payload == PSF_PAYLOAD_SH2_YCOCG) {
     L.sh = off;
     off = align_up(off + S * sizeof(psf::ShState), 256);
@@ -210,8 +216,10 @@ Layout layout_of(const psf_config& c) {
   if (c.flags & PSF_FLAG_TRACK_VARIANCE) {
     L.var = off;
     off = align_up(off + S * 4, 256);
-    L.acc_q = off;
-    off = align_up(off + S * 8, 256);
+    if (!no_acc) {
+      L.acc_q = off;
+      off = align_up(off + S * 8, 256);
+    }
   }
   if (L.part) {
     const uint64_t tile = psf::bin_tile(c.bin_per ? c.bin_per : kDefaultBinPer);
@@ -353,7 +361,12 @@ PSF_API size_t psf_table_bytes(const psf_config* cfg) {
     g_err = why;
     return 0;
   }
-  return layout_of(*cfg).total;
+  const Layout L = layout_of(*cfg);
+  if ((cfg->flags & PSF_FLAG_NO_ACCUMULATORS) && !L.part) {
+    g_err = "a table without accumulators needs the partitioned strategy (too many partitions)";
+    return 0;
+  }
+  return L.total;
 }
 
 PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, size_t buffer_bytes,
@@ -368,6 +381,8 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   if ((cfg->flags & PSF_FLAG_TRACK_VARIANCE) && (cfg->payload != PSF_PAYLOAD_RGB || cfg->weighted))
     return fail(PSF_NOT_SUPPORTED, "the luminance variance is kept for unweighted RGB tables only");
   const Layout L = layout_of(*cfg);
+  if ((cfg->flags & PSF_FLAG_NO_ACCUMULATORS) && !L.part)
+    return fail(PSF_NOT_SUPPORTED, "a table without accumulators needs the partitioned strategy (too many partitions)");
   if (device_buffer) {
     if (buffer_bytes < L.total)
       return fail(PSF_BUFFER_TOO_SMALL, "device buffer smaller than psf_table_bytes(cfg)");
@@ -394,7 +409,7 @@ PSF_API psf_status psf_create_table(const psf_config* cfg, void* device_buffer, 
   t->tv.touch = reinterpret_cast<psf::BlockTouch*>(b + L.touch);
   t->tv.slots = reinterpret_cast<psf::Slot*>(b + L.slots);
   t->tv.keys = reinterpret_cast<unsigned long long*>(b + L.keys);
-  t->tv.acc = reinterpret_cast<psf::Acc*>(b + L.acc);
+  t->tv.acc = L.acc ? reinterpret_cast<psf::Acc*>(b + L.acc) : nullptr;
   t->tv.sh = L.sh ? reinterpret_cast<psf::ShState*>(b + L.sh) : nullptr;
   t->tv.sh_acc = L.sh_acc ? reinterpret_cast<psf::ShAcc*>(b + L.sh_acc) : nullptr;
   t->tv.var = L.var ? reinterpret_cast<float*>(b + L.var) : nullptr;
@@ -466,6 +481,7 @@ PSF_API psf_status psf_insert_samples(psf_table* t, const psf_records* rec, uint
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
   if (n == 0) return PSF_OK;
   if (!rec_ok(rec, t, &why)) return fail(PSF_INVALID_ARGUMENT, why);
+  if (!t->tv.acc) return fail(PSF_NOT_SUPPORTED, "separate inserts on a table without accumulators");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   return do_insert(t, rec_ptrs(rec), n, s);
@@ -473,6 +489,7 @@ PSF_API psf_status psf_insert_samples(psf_table* t, const psf_records* rec, uint
 
 PSF_API psf_status psf_temporal_update(psf_table* t, psf_stream stream) {
   if (!t) return fail(PSF_INVALID_ARGUMENT, "table is NULL");
+  if (!t->tv.acc) return fail(PSF_NOT_SUPPORTED, "separate updates on a table without accumulators");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   t->last = s;
   return do_update(t, s);
@@ -524,6 +541,12 @@ PSF_API psf_status psf_iterate(psf_table* t, const psf_records* rec, uint64_t n,
       e = timed(t, PSF_K_QUERY, s, [&] { return psf::launch_unstage(n, t->tv, pv, d_out_rgb, d_out_found, s); });
       return e == hipSuccess ? PSF_OK : hip_fail(e, "query launch");
     }
+  } else if (!t->tv.acc) {
+    // no accumulators: nothing to blend without records, and a launch past
+    // the staging capacity would need the separate insert and update
+    if (n > 0) return fail(PSF_NOT_SUPPORTED, "more records than max_batch on a table without accumulators");
+    t->updates++;
+    t->touch_entries = 0;
   } else {
     if (n > 0) st = do_insert(t, rec_ptrs(rec), n, s);
     if (st == PSF_OK) st = do_update(t, s);

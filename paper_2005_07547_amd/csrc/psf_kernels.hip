@@ -357,11 +357,9 @@ __global__ void k_clear(TableView tv, uint64_t nslots) {
     z.L[0] = z.L[1] = z.L[2] = z.L[3] = 0;
     tv.slots[s] = z;
     tv.keys[s] = kEmpty;
-    tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
-    if (tv.var) {
-      tv.var[s] = 0.0f;
-      tv.acc_q[s] = 0.0;
-    }
+    if (tv.acc) tv.acc[s] = Acc{0u, {0.0f, 0.0f, 0.0f}};
+    if (tv.var) tv.var[s] = 0.0f;
+    if (tv.acc_q) tv.acc_q[s] = 0.0;
   }
 }
 
@@ -428,7 +426,7 @@ __global__ void k_compact(TableView tv, uint64_t nslots, int32_t dtype, unsigned
     const unsigned long long at = atomicAdd(cursor, 1ull);
     if (at >= cap) continue;
     keys[at] = sl.key;
-    n_new[at] = tv.acc[s].n;
+    n_new[at] = tv.acc ? tv.acc[s].n : 0u;
     c_old[at] = sl.c_old;
     float r, g, b;
     load_state(sl, dtype, r, g, b);

@@ -24,6 +24,7 @@ PSF_FLAG_PROBE_STATS = 1
 PSF_FLAG_TIMING = 2
 PSF_FLAG_TRANSPOSE_RUNS = 4
 PSF_FLAG_TRACK_VARIANCE = 8
+PSF_FLAG_NO_ACCUMULATORS = 16
 PSF_K_COUNT = 11
 PSF_EST_CV, PSF_EST_BIASED = 0, 1
 PSF_PRIM_QUAD, PSF_PRIM_SPHERE = 0, 1

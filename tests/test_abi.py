@@ -49,6 +49,33 @@ def test_host_side_validation_without_gpu():
     assert lib.psf_version().startswith(b"psf")
 
 
+def test_table_without_accumulators_bytes():
+    """PSF_FLAG_NO_ACCUMULATORS leaves out the 16-byte per-slot frame
+    accumulator (and the 8-byte pending squared-luminance sum of a variance
+    table); it needs the RGB payload and the partitioned strategy."""
+    from paper_2005_07547_amd import psf
+    lib = psf.load()
+
+    def nbytes(**kw):
+        return lib.psf_table_bytes(ctypes.byref(psf.make_config(**kw)))
+
+    S = 1 << 20
+    plain = nbytes(log2_slots=20, max_batch=1 << 18)
+    lean = nbytes(log2_slots=20, max_batch=1 << 18, flags=psf.PSF_FLAG_NO_ACCUMULATORS)
+    assert plain - lean == S * 16
+    var = psf.PSF_FLAG_TRACK_VARIANCE
+    assert (nbytes(log2_slots=20, max_batch=1 << 18, flags=var)
+            - nbytes(log2_slots=20, max_batch=1 << 18, flags=var | psf.PSF_FLAG_NO_ACCUMULATORS)) == S * 24
+    assert nbytes(log2_slots=20, flags=psf.PSF_FLAG_NO_ACCUMULATORS, insert_mode=psf.PSF_INSERT_DIRECT) == 0
+    assert b"partitioned" in lib.psf_last_error()
+    assert nbytes(log2_slots=20, flags=psf.PSF_FLAG_NO_ACCUMULATORS, payload=psf.PSF_PAYLOAD_SH2_YCOCG,
+                  insert_mode=psf.PSF_INSERT_DIRECT) == 0
+    # more partitions than the partitioned strategy takes (2^28 slots of 2^11)
+    assert nbytes(log2_slots=28, part_log2=11, flags=psf.PSF_FLAG_NO_ACCUMULATORS) == 0
+    assert b"partitioned strategy" in lib.psf_last_error()
+    assert nbytes(log2_slots=20, flags=32) == 0
+
+
 def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structures against the C layouts of include/psf.h,
     compiled by the host C compiler."""
