@@ -54,18 +54,33 @@ class SessionRequest:
     latencies_ms: list = field(default_factory=list)
 
 
-def table_footprint(cfg: dict, records: int) -> int:
+def session_table_cfg(cfg: dict, records: int, lean: bool = True) -> dict:
+    """The table configuration a session is served with: staging sized to
+    its records, and, where the configuration allows it, no frame
+    accumulators (a served session only ever takes fused iterations)."""
+    import ctypes
+    lib = psf.load()
+    out = dict(cfg, max_batch=max(1, records))
+    if lean:
+        trial = dict(out, flags=int(out.get("flags", 0)) | psf.PSF_FLAG_NO_ACCUMULATORS)
+        if lib.psf_table_bytes(ctypes.byref(psf.make_config(**trial))):
+            out = trial
+    return out
+
+
+def table_footprint(cfg: dict, records: int, lean: bool = True) -> int:
     """Device bytes a session holds while resident: its table plus its output
     buffers (inputs are shared pools)."""
     import ctypes
     lib = psf.load()
-    c = psf.make_config(**dict(cfg, max_batch=max(1, records)))
+    c = psf.make_config(**session_table_cfg(cfg, records, lean))
     return int(lib.psf_table_bytes(ctypes.byref(c))) + records * 13
 
 
 class Server:
-    def __init__(self, budget_bytes: int, max_active: int = 64, keep_tables: bool = False):
+    def __init__(self, budget_bytes: int, max_active: int = 64, keep_tables: bool = False, lean: bool = True):
         import torch
+        self.lean = bool(lean)
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.batch = psf.Batch(max_active)
@@ -82,7 +97,7 @@ class Server:
 
     def _admit(self, s: SessionRequest, now: float):
         torch = self._torch
-        s.table = psf.Table(**dict(s.table_cfg, max_batch=max(1, s.records)))
+        s.table = psf.Table(**session_table_cfg(s.table_cfg, s.records, self.lean))
         s.out = torch.empty((3, s.records), dtype=torch.float32, device="cuda")
         s.found = torch.empty(s.records, dtype=torch.uint8, device="cuda")
         s.admitted_at = now
@@ -113,7 +128,7 @@ class Server:
         torch = self._torch
         pending = sorted(requests, key=lambda r: r.arrival)
         for r in pending:
-            r.footprint = table_footprint(r.table_cfg, r.records)
+            r.footprint = table_footprint(r.table_cfg, r.records, self.lean)
             if r.footprint > self.budget:
                 raise ValueError(f"session {r.sid} needs {r.footprint} bytes, above the budget")
         waiting: list = []

@@ -64,6 +64,11 @@ def test_results_same_alone_and_in_the_mix(env):
         assert r.table.stats()["updates"] == r.iterations
         assert r.table.stats()["dropped"] == 0
         assert len(r.latencies_ms) == r.iterations
+        # served without frame accumulators: 16 bytes per slot less
+        assert r.table.cfg.flags & psf.PSF_FLAG_NO_ACCUMULATORS
+        assert alone.nbytes - r.table.nbytes == 16 << int(r.table_cfg["log2_slots"])
+        assert r.footprint == serving.table_footprint(r.table_cfg, r.records, lean=False) - alone.nbytes + \
+            r.table.nbytes
         orc = oracle.Oracle(**r.table_cfg)
         for it in range(r.iterations):
             orc.insert(r.host_frames[it % len(r.host_frames)])
