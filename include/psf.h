@@ -116,9 +116,11 @@ enum {
  * out the 16-byte per-slot accumulator (and, with
  * PSF_FLAG_TRACK_VARIANCE, the 8-byte pending squared-luminance sum):
  * 40 bytes per slot for the cell state and key mirror instead of 56.
- * Requirements: RGB payload and an insert_mode other than DIRECT, and a
- * table narrow enough for the partitioned strategy (psf_table_bytes
- * returns 0 and psf_create_table NOT_SUPPORTED otherwise).  On such a table
+ * Requirements: RGB payload and an insert_mode other than DIRECT
+ * (psf_table_bytes returns 0 and psf_create_table INVALID_ARGUMENT
+ * otherwise), and a table narrow enough for the partitioned strategy, at
+ * most 2^14 partitions (psf_table_bytes returns 0 and psf_create_table
+ * NOT_SUPPORTED otherwise).  On such a table
  * psf_insert_samples and psf_temporal_update return NOT_SUPPORTED, as does
  * psf_iterate with more records than max_batch (a launch that would be
  * split); psf_iterate with no records blends nothing and only answers the
