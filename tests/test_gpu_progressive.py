@@ -24,13 +24,16 @@ def _dev_arrays(arrs):
     return tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs)
 
 
-@pytest.mark.parametrize("insert_mode", [1, 2])
-def test_furnace_frames_match_the_oracle(env, insert_mode):
+# direct and partitioned strategies; the partitioned one also on a table
+# without frame accumulators (flags 16, PSF_FLAG_NO_ACCUMULATORS)
+@pytest.mark.parametrize("insert_mode,flags", [(1, 0), (2, 0), (2, 16)], ids=["direct", "partitioned", "lean"])
+def test_furnace_frames_match_the_oracle(env, insert_mode, flags):
     import oracle
     from synth import workloads as W
     torch, psf = env
     cfg = W.furnace_table()
-    t = psf.Table(**dict(cfg, insert_mode=insert_mode))
+    t = psf.Table(**dict(cfg, insert_mode=insert_mode, flags=flags))
+    assert flags == 0 or (flags & psf.PSF_FLAG_NO_ACCUMULATORS and not t.export()["n_new"].any())
     o = oracle.Oracle(**cfg)
     for it in range(40):
         x, nx, tp, em = W.furnace_paths(2048, 2, it)
