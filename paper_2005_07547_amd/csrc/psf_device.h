@@ -115,7 +115,10 @@ __device__ __forceinline__ float counter_value(uint32_t c, bool wtd) {
   return wtd ? __uint_as_float(c) : (float)c;
 }
 
-// c_old + n as a counter word (the weight sum rounds once, to binary32).
+// c_old + n as a counter word.  In a weighted table both are binary32 weight
+// sums and this addition rounds once; the frame's sum n is itself rounded
+// once from binary64 by the partitioned merge, but accumulated with binary32
+// atomics (in no fixed order) by the direct insert.
 __device__ __forceinline__ uint32_t counter_add(uint32_t c, uint32_t n, bool wtd) {
   return wtd ? __float_as_uint(__uint_as_float(c) + __uint_as_float(n)) : c + n;
 }
