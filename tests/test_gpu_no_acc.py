@@ -127,3 +127,38 @@ def test_lean_tables_in_a_batch(env):
         tl.close()
         tf.close()
     batch.close()
+
+
+@pytest.mark.parametrize("state_dtype", [3, 4], ids=["F16_EF", "BF16_EF"])
+def test_lean_table_with_16_bit_state(env, state_dtype):
+    """The 16-bit formats with error feedback keep their rounding residual
+    in the slot, not in the accumulator: a lean table's cells and answers
+    equal an ordinary table's of the same format (to one rounding of the
+    format, should the binary64 sums' atomic order ever flip one)."""
+    from tests.helpers import STATE_BOUND
+    torch, psf = env
+    wl, sc = _workload()
+    cfg = dict(wl["table"], state_dtype=state_dtype)
+    frames = [to_device(sc.generate(wl["gen"], it)) for it in range(3)]
+    n = int(frames[0]["px"].numel())
+    lean = psf.Table(**dict(cfg, max_batch=n, flags=psf.PSF_FLAG_NO_ACCUMULATORS))
+    full = psf.Table(**dict(cfg, max_batch=n))
+    tol = STATE_BOUND[state_dtype]
+    tiny = 2.0 ** -24 if state_dtype == 3 else 2.0 ** -133  # smallest subnormal step
+
+    def close(a, b):
+        a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        return bool((np.abs(a - b) <= tol * np.abs(b) + tiny).all())
+
+    for f in frames:
+        out_l, fnd_l = lean.iterate(f)
+        out_f, fnd_f = full.iterate(f)
+        torch.cuda.synchronize()
+        assert np.array_equal(fnd_l.cpu().numpy(), fnd_f.cpu().numpy())
+        assert close(out_l.cpu().numpy(), out_f.cpu().numpy())
+    el, ef = lean.export(), full.export()
+    assert np.array_equal(el["keys"], ef["keys"])
+    assert np.array_equal(el["c_old"], ef["c_old"])
+    assert close(el["L"], ef["L"])
+    lean.close()
+    full.close()
